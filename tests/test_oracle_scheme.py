@@ -1,0 +1,155 @@
+"""Pins for the oracle's Lax-Wendroff step (Eqs. 13-14) and its boundary rules.
+
+Invariants the mathematics fixes: linearity, exact zero propagation, Dirichlet
+columns, the m -> -m / theta -> pi - theta conjugate mirror of Eq. (1), a -> 0
+continuity, second-order self-convergence, the stability of the step matrix at
+the stability-derived dt (and its blow-up at dt = dr*/2), and the exactness of
+windowed evaluation inside the domain of dependence.
+"""
+import numpy as np
+import pytest
+
+from paper_0909_4039_amd import inputs
+
+KW = dict(nr=40, nth=12, rstar_min=-30.0, rstar_max=60.0, M=1.0)
+
+
+def make(oracle_mod, a=0.9, m=2, s=-2, dt=0.01, amp=0.0, r0=10.0, **kw):
+    p = dict(KW)
+    p.update(kw)
+    return oracle_mod.Oracle(p["nr"], p["nth"], p["rstar_min"], p["rstar_max"], a, p["M"], m, s, dt,
+                             r0=r0, amp=amp, rstar_obs=20.0)
+
+
+def test_linearity_and_zero(oracle_mod):
+    o = make(oracle_mod)
+    u1 = inputs.random_state(KW["nr"], KW["nth"], 1)
+    u2 = inputs.random_state(KW["nr"], KW["nth"], 2)
+    al, be = 0.7 - 0.2j, -1.3 + 0.5j
+    a1 = o.step(*u1, 0.3)
+    a2 = o.step(*u2, 0.3)
+    a3 = o.step(al * u1[0] + be * u2[0], al * u1[1] + be * u2[1], 0.3)
+    for k in range(2):
+        ref = al * a1[k] + be * a2[k]
+        assert np.max(np.abs(a3[k] - ref)) < 1e-12 * np.max(np.abs(ref))
+    z = np.zeros((KW["nth"], KW["nr"]), complex)
+    p, q = o.step(z, z, 0.3)
+    assert not np.any(p) and not np.any(q)
+    # Dirichlet r* columns are exactly zero after a step
+    assert not np.any(a1[0][:, 0]) and not np.any(a1[0][:, -1])
+    assert not np.any(a1[1][:, 0]) and not np.any(a1[1][:, -1])
+
+
+def test_source_is_affine_in_amp(oracle_mod):
+    z = np.zeros((KW["nth"], KW["nr"]), complex)
+    u = inputs.random_state(KW["nr"], KW["nth"], 3)
+    o0 = make(oracle_mod, amp=0.0)
+    o1 = make(oracle_mod, amp=1.0)
+    o2 = make(oracle_mod, amp=2.5)
+    s1 = o1.step(z, z, 1.7)
+    s2 = o2.step(z, z, 1.7)
+    assert np.max(np.abs(s2[1] - 2.5 * s1[1])) < 1e-14 * np.max(np.abs(s2[1]))
+    assert np.max(np.abs(s1[1])) > 0
+    full = o1.step(*u, 1.7)
+    hom = o0.step(*u, 1.7)
+    assert np.max(np.abs(full[1] - hom[1] - s1[1])) < 1e-12 * np.max(np.abs(full[1]))
+
+
+@pytest.mark.parametrize("m", [2, 1, 3])
+def test_conjugate_mirror_symmetry(oracle_mod, m):
+    # Eq. (1) maps to itself under m -> -m, theta -> pi - theta, complex conjugation
+    nr, nth = KW["nr"], KW["nth"]
+    phi, pi = inputs.smooth_random_state(nr, nth, KW["rstar_min"], KW["rstar_max"], 5)
+    op = make(oracle_mod, a=0.9, m=m, amp=1.0, dt=0.02)
+    om = make(oracle_mod, a=0.9, m=-m, amp=1.0, dt=0.02)
+    p1, q1, w1 = op.run(phi, pi, 60)
+    p2, q2, w2 = om.run(np.conj(phi[::-1]), np.conj(pi[::-1]), 60)
+    scale = np.max(np.abs(p1))
+    assert np.max(np.abs(p2 - np.conj(p1[::-1]))) < 1e-13 * scale
+    assert np.max(np.abs(q2 - np.conj(q1[::-1]))) < 1e-13 * np.max(np.abs(q1))
+
+
+def test_a_to_zero_continuity(oracle_mod):
+    phi, pi = inputs.smooth_random_state(KW["nr"], KW["nth"], KW["rstar_min"], KW["rstar_max"], 6)
+    o0 = make(oracle_mod, a=0.0, amp=1.0)
+    o1 = make(oracle_mod, a=1e-8, amp=1.0)
+    o2 = make(oracle_mod, a=2e-8, amp=1.0)
+    r0 = o0.run(phi, pi, 50)[0]
+    r1 = o1.run(phi, pi, 50)[0]
+    r2 = o2.run(phi, pi, 50)[0]
+    d1 = np.max(np.abs(r1 - r0))
+    d2 = np.max(np.abs(r2 - r0))
+    assert d1 < 1e-6 * np.max(np.abs(r0))
+    assert d2 / d1 == pytest.approx(2.0, rel=0.05)     # O(a)
+
+
+def test_second_order_self_convergence(oracle_mod):
+    # refine r* and t together (dt = 0.02 dr*), fixed theta grid, Kerr with source
+    a, m, s = 0.9, 2, -2
+    sols = []
+    T = 10.0
+    for nr in (201, 401, 801):
+        dr = 200.0 / (nr - 1)
+        dt = 0.02 * dr
+        o = oracle_mod.Oracle(nr, 16, -50.0, 150.0, a, 1.0, m, s, dt, r0=10.0, amp=1.0,
+                              sigma_r_cells=4.0 / dr, sigma_th_cells=2.0, rstar_obs=20.0)
+        phi, pi = inputs.pulse(nr, 16, -50.0, 150.0, m, 20.0, 8.0, 1.0)
+        p, q, _ = o.run(phi, pi, int(round(T / dt)), record=False)
+        sols.append(p)
+    c, mdl, f = sols[0], sols[1][:, ::2], sols[2][:, ::4]
+    ratio = np.linalg.norm(c - mdl) / np.linalg.norm(mdl - f)
+    assert 3.6 < ratio < 4.4, ratio
+
+
+def _assemble(o, shape, t=0.0):
+    nth, nr = shape
+    n = nth * nr
+    K = np.zeros((4 * n, 4 * n))
+    z = np.zeros(shape, complex)
+    col = 0
+    for field in range(2):
+        for unit in (1.0, 1j):
+            for k in range(n):
+                e = np.zeros(n, complex)
+                e[k] = unit
+                e = e.reshape(shape)
+                p, q = o.step(e, z, t) if field == 0 else o.step(z, e, t)
+                K[:, col] = np.concatenate([p.real.ravel(), p.imag.ravel(), q.real.ravel(), q.imag.ravel()])
+                col += 1
+    return K
+
+
+def test_stability_probe(oracle_mod):
+    nr, nth = 24, 8
+    rmin, rmax = -30.0, 60.0
+    a, m, s = 0.9, 2, -2
+    dt_stable = oracle_mod.stable_dt(nr, nth, rmin, rmax, a, 1.0, m, s, 10000)
+    dr = (rmax - rmin) / (nr - 1)
+    o1 = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, dt_stable)
+    rho1 = np.max(np.abs(np.linalg.eigvals(_assemble(o1, (nth, nr)))))
+    o2 = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, 0.5 * dr)
+    rho2 = np.max(np.abs(np.linalg.eigvals(_assemble(o2, (nth, nr)))))
+    assert rho1 <= 1.0 + 1.0 * dt_stable, (rho1, dt_stable)
+    assert rho2 > 2.0, rho2
+
+
+def test_window_domain_of_dependence(oracle_mod):
+    nr, nth, n = 60, 24, 3
+    rmin, rmax = -40.0, 80.0
+    a, m, s, dt = 0.6, 2, -2, 0.02
+    phi, pi = inputs.random_state(nr, nth, 9)
+    full = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, dt, r0=10.0, amp=1.0, rstar_obs=0.0)
+    pf, qf, _ = full.run(phi, pi, n, t_start=0.4, record=False)
+    for (i0, ni, j0, nj) in [(10, 30, 5, 14), (0, 20, 0, 12), (35, 25, 12, 12)]:
+        w = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, dt, r0=10.0, amp=1.0,
+                              rstar_obs=0.0, window=(i0, ni, j0, nj))
+        sl = (slice(j0, j0 + nj), slice(i0, i0 + ni))
+        pw, qw, _ = w.run(phi[sl], pi[sl], n, t_start=0.4, record=False)
+        ok = np.isfinite(pw)
+        assert np.array_equal(pw[ok], pf[sl][ok]) and np.array_equal(qw[ok], qf[sl][ok])
+        # the cone interior must be finite: n columns and 2n rows in from cut edges
+        ilo = 0 if i0 == 0 else n
+        ihi = ni if i0 + ni == nr else ni - n
+        jlo = 0 if j0 == 0 else 2 * n
+        jhi = nj if j0 + nj == nth else nj - 2 * n
+        assert ok[jlo:jhi, ilo:ihi].all()
