@@ -1,0 +1,132 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused Lax-Wendroff Teukolsky step on one MI355X.
+
+A bench "step" is one time step of the whole hot path over the full grid:
+predictor and corrector (paper Eqs. 13-14) with the coefficients of
+Eqs. (5)-(12), the particle source, the boundary conditions and the
+waveform recorder, all in the library's fused kernel.  The workload is the
+largest single-mode grid: a = 0.99, m = 2, s = -2, source at r0 = 8,
+32768 x 1024 (r*, theta) points, zero initial data.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+BYTES_PER_UPDATE = {64: 64, 32: 32}   # read (Phi, Pi) + write (Phi', Pi'), complex
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def time_solver(W, prec, steps, warmup):
+    import torch
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+    s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
+    s.set_source(W.r0, W.amp)
+    s.set_observer(W.rstar_obs, warmup + steps + 1)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    stream = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.check_finite()
+    ms = e0.elapsed_time(e1)
+    rows = s.params
+    s.close()
+    return ms, dt
+
+
+def cpu_baseline(W, seconds):
+    import numpy as np
+    import oracle
+    from paper_0909_4039_amd import inputs
+    oracle.build()
+    j0, nj = W.nth // 2 - 32, 64
+    dt = oracle.stable_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+    o = oracle.Oracle(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, r0=W.r0, amp=W.amp,
+                      rstar_obs=W.rstar_obs, window=(0, W.nr, j0, nj))
+    phi = np.zeros((nj, W.nr), complex)
+    pi = np.zeros((nj, W.nr), complex)
+    t = time.perf_counter()
+    phi, pi = o.step(phi, pi, 0.0)
+    one = time.perf_counter() - t
+    n = max(1, int(seconds / max(one, 1e-6)) - 1)
+    t = time.perf_counter()
+    for k in range(n):
+        phi, pi = o.step(phi, pi, (k + 1) * dt)
+    el = time.perf_counter() - t
+    pts = W.nr * nj
+    return {"value": pts * n / el, "unit": "grid-point updates/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"theta rows {j0}-{j0 + nj - 1} of the {W.nr}x{W.nth} grid ({pts} points), all r* "
+                      f"columns, {n} FP64 steps ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU "
+              "path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_0909_4039_amd import workloads
+    W = workloads.LARGE
+    pts = W.nr * W.nth
+    ms, dt = time_solver(W, 64, args.steps, args.warmup)
+    ms_step = ms / args.steps
+    ups = pts * args.steps / (ms * 1e-3)
+    achieved = BYTES_PER_UPDATE[64] * pts / (ms_step * 1e-3)
+    out = {
+        "metric": "grid-point updates/s FP64/FP32 + % HBM roofline; batched vs per-mode; adjoint/fwd",
+        "value": ups,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": W.name, "n_rstar": W.nr, "n_theta": W.nth, "rstar": [W.rstar_min, W.rstar_max],
+                   "a": W.a, "m": W.m, "s": W.s, "r0": W.r0, "rstar_obs": W.rstar_obs, "dt": dt,
+                   "initial_data": "zero, source on"},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "kernel": "lw_step_kernel<double>",
+                     "bytes_per_launch": BYTES_PER_UPDATE[64] * pts},
+    }
+    if not args.no_fp32:
+        ms32, _ = time_solver(W, 32, args.steps, args.warmup)
+        ups32 = pts * args.steps / (ms32 * 1e-3)
+        out["fp32"] = {"value": ups32, "ms_per_step": ms32 / args.steps,
+                       "hbm_frac": BYTES_PER_UPDATE[32] * pts / (ms32 / args.steps * 1e-3) / HBM_PEAK}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,149 @@
+/*
+ * teuk.h -- C ABI of libteuk, an MI355X (gfx950) library that evolves one
+ * azimuthal mode of the Teukolsky equation on an (r*, theta) grid with the
+ * two-step Lax-Wendroff scheme.
+ *
+ * Paper: G. Khanna and J. McKennon, "An exploration of CUDA and CBEA for a
+ * gravitational wave source-modelling application".  The problem statement
+ * is Sec. 2: Eq. (1) (Teukolsky master equation, spin weight s, Kerr
+ * parameter a, mass M, source T), the tortoise/azimuthal coordinates of
+ * Eqs. (2)-(3), the m-mode ansatz Eq. (4), the first-order system
+ * Eqs. (5)-(12) for u = (Phi, Pi), the Lax-Wendroff predictor/corrector
+ * Eqs. (13)-(14), centred angular differences and the boundary conditions
+ * stated after Eq. (14), and the waveform read at an extraction radius
+ * (Sec. 2.2, Fig. 1).
+ *
+ * Conventions shared by every call:
+ *   - Fields are complex and stored as interleaved (re, im) pairs, row-major
+ *     [n_theta][n_rstar] with r* contiguous: complex128 for TEUK_FP64,
+ *     complex64 for TEUK_FP32 (torch.complex128 / torch.complex64 layout).
+ *   - Grid: r*_i = rstar_min + i dr*, dr* = (rstar_max - rstar_min)/(n_rstar - 1);
+ *     theta_j = (j + 1/2) pi / n_theta (cell-centred, poles excluded).
+ *   - Every pointer named "device" must point to device memory of the GPU
+ *     that was current at teuk_create; it stays owned by the caller.  The
+ *     library allocates only its own coefficient tables (about 200 B per
+ *     r* node and 64 B per theta row) at teuk_create and frees them in
+ *     teuk_destroy.
+ *   - Calls are asynchronous on the stream given at create unless noted.
+ *   - Return value: TEUK_OK (0) or a negative TEUK_E* code.  No C++
+ *     exception crosses the ABI.  A context is not thread safe; use one
+ *     context per stream.
+ */
+#ifndef TEUK_H
+#define TEUK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEUK_OK 0
+#define TEUK_EINVAL (-1)    /* an argument is out of range                     */
+#define TEUK_ESTATE (-2)    /* call out of order (e.g. no state bound)         */
+#define TEUK_EDEVICE (-3)   /* a HIP call failed; teuk_last_error has the text */
+#define TEUK_EUNSTABLE (-4) /* non-finite values found in the state            */
+#define TEUK_ENOTSUP (-5)   /* valid request this build does not serve         */
+
+#define TEUK_FP64 64
+#define TEUK_FP32 32
+
+typedef struct teuk_ctx teuk_ctx;
+
+typedef struct {
+    int64_t n_rstar;   /* r* nodes, >= 4                */
+    int64_t n_theta;   /* theta cells, >= 4             */
+    double rstar_min;  /* first r* node                 */
+    double rstar_max;  /* last r* node, > rstar_min     */
+} teuk_grid;
+
+/* Create a solver for one (a, M, m, s) mode (Eq. 1, ansatz Eq. 4) with time
+ * step dt on grid g.  prec is TEUK_FP64 or TEUK_FP32 (storage and
+ * arithmetic).  hip_stream is a hipStream_t (NULL: the null stream).
+ * Requires M > 0, 0 <= a < M, |s| <= 2, dt > 0.  Builds the radial tables
+ * (r(r*) from Eq. 2 solved in ln(r - r+)) on the host in FP64 and uploads
+ * them.  On success *out receives the context; on failure *out is NULL. */
+int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, double dt,
+                int32_t prec, void* hip_stream, teuk_ctx** out);
+
+/* Release the context and its tables (synchronises its stream first). */
+int teuk_destroy(teuk_ctx* ctx);
+
+/* Bind caller-owned device state: phi, pi hold u^n; phi_next, pi_next are
+ * the ping-pong partners.  All four must be distinct, n_theta*n_rstar
+ * complex elements each.  teuk_step alternates between the two pairs;
+ * teuk_current tells which pair holds the latest state.  Binding resets
+ * the current pair to (phi, pi). */
+int teuk_bind_state(teuk_ctx* ctx, void* phi, void* pi, void* phi_next, void* pi_next);
+
+/* Particle source (stand-in for the paper's T, which it does not print):
+ * T_Pi = amp exp(-(r*-r*(r0))^2/(2 sr^2)) exp(-(theta-pi/2)^2/(2 sth^2)) e^{-i m Omega t},
+ * T_Phi = 0, with sr = sigma_r_cells dr*, sth = sigma_th_cells dtheta and
+ * Omega = sqrt(M)/(r0^{3/2} + a sqrt(M)) (circular equatorial orbit).
+ * Requires r0 > r+ and positive widths; amp = 0 switches the source off. */
+int teuk_set_source(teuk_ctx* ctx, double r0, double amp, double sigma_r_cells,
+                    double sigma_th_cells);
+
+/* Waveform recorder: from now on each step records
+ * w_j = (1 - alpha) Phi_{i0,j} + alpha Phi_{i0+1,j}, r*_obs = r*_{i0} + alpha dr*,
+ * into wave[k][n_theta] (device, complex, caller-owned) where k counts
+ * steps from the current step (row 0 = current state).  Rows at or past
+ * capacity_rows are not written.  rstar_obs must lie strictly inside the
+ * grid.  wave = NULL switches recording off. */
+int teuk_set_observer(teuk_ctx* ctx, double rstar_obs, void* wave, int64_t capacity_rows);
+
+/* Advance n >= 0 steps of Eqs. (13)-(14) with the source fused and the
+ * boundary conditions applied; records rows 0..n (relative to the step
+ * count at entry) when an observer is set. */
+int teuk_step(teuk_ctx* ctx, int64_t n);
+
+/* Write the waveform of the current state at rstar_obs into out
+ * (device, n_theta complex). */
+int teuk_extract(teuk_ctx* ctx, double rstar_obs, void* out);
+
+/* Host-side time bookkeeping: t = t0 + (step - step0) dt. */
+int teuk_get_time(teuk_ctx* ctx, double* t, int64_t* step);
+int teuk_set_time(teuk_ctx* ctx, double t, int64_t step);
+
+/* 0: the latest state is in (phi, pi); 1: in (phi_next, pi_next);
+ * negative: error code. */
+int teuk_current(teuk_ctx* ctx);
+
+/* Tile shape of the step kernel: rows_per_wave theta rows per wavefront
+ * (1..4096).  0 restores the default. */
+int teuk_set_tiling(teuk_ctx* ctx, int32_t rows_per_wave);
+
+/* Scan the current state for non-finite values (synchronous).  Returns
+ * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */
+int teuk_check_finite(teuk_ctx* ctx);
+
+/* Sticky status of the context (TEUK_OK if no call has failed). */
+int teuk_status(teuk_ctx* ctx);
+
+/* Text of the last failure of this context ("" if none). */
+const char* teuk_last_error(teuk_ctx* ctx);
+
+/* Name of an error code. */
+const char* teuk_strerror(int code);
+
+/* Suggested time step for n_steps steps of the explicit scheme (host only,
+ * synchronous).  For data smooth in r* both Lax-Wendroff stages apply the
+ * angular terms of S (Eq. 12), which acts on a theta-mode of frequency w as
+ * the explicit midpoint rule with |G|^2 = 1 + (w dt)^4 / 4; the rule keeps
+ * the growth of the stiffest mode to one e-fold over the run:
+ * dt = min(dr* / 2, (8/n_steps)^(1/4) / w_max), with w_max^2 bounded by the
+ * Gershgorin bound of the discrete angular operator times max Delta/Sigma^2. */
+int teuk_suggest_dt(const teuk_grid* g, double a, double M, int32_t m, int32_t s,
+                    int64_t n_steps, double* dt_out);
+
+/* Geometry probe (host only): r*(r) from Eq. (2) and its inverse as
+ * delta = r - r+. */
+double teuk_rstar_of_r(double r, double a, double M);
+double teuk_delta_of_rstar(double rstar, double a, double M);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEUK_H */

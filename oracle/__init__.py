@@ -77,6 +77,7 @@ def _L():
             "teuko_dr": (D, [P]), "teuko_dth": (D, [P]), "teuko_rstar0": (D, [P]),
             "teuko_Omega": (D, [P]), "teuko_iobs": (I64, [P]), "teuko_alpha": (D, [P]),
             "teuko_max_DoS2": (D, [P]),
+            "teuko_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -91,6 +92,11 @@ def _ptr(a: np.ndarray):
 
 
 # ------------------------------------------------------------ Eq. (2)
+
+def threads() -> int:
+    """OpenMP threads the oracle's step loops use."""
+    return _L().teuko_threads()
+
 
 def rstar_of_r(r: float, a: float, M: float = 1.0) -> float:
     """Tortoise coordinate r*(r), Eq. (2) integrated with the standard constant."""

@@ -626,3 +626,11 @@ double teuko_max_DoS2(const teuko_ctx* c) {
     }
     return mx;
 }
+
+/* Number of OpenMP threads the step loops use. */
+#ifdef _OPENMP
+#include <omp.h>
+int teuko_threads(void) { return omp_get_max_threads(); }
+#else
+int teuko_threads(void) { return 1; }
+#endif

@@ -1,0 +1,161 @@
+// Host-side geometry of libteuk: the tortoise map (paper Eq. 2), the radial
+// coefficient numerators of the first-order system (Eqs. 5-12) and the
+// angular difference weights (centred second differences on a cell-centred
+// theta grid, with the pole rule stated after Eq. 14).  FP64, built once
+// per context and uploaded.
+#include <algorithm>
+#include <cmath>
+
+#include "teuk_internal.h"
+
+namespace teuk {
+
+static void horizons(double a, double M, double& rp, double& rm) {
+    double q = std::sqrt(M * M - a * a);
+    rp = M + q;
+    rm = M - q;
+}
+
+// Eq. (2) integrated: r* = r + 2M r+/(r+-r-) ln((r-r+)/2M) - 2M r-/(r+-r-) ln((r-r-)/2M),
+// written in delta = r - r+ so that the horizon limit keeps its precision.
+double rstar_of_delta(double delta, double a, double M) {
+    double rp, rm;
+    horizons(a, M, rp, rm);
+    double k = rp - rm;
+    double v = rp + delta + (2.0 * M * rp / k) * std::log(delta / (2.0 * M));
+    if (rm > 0.0) v -= (2.0 * M * rm / k) * std::log((delta + k) / (2.0 * M));
+    return v;
+}
+
+// Solve r*(delta) = rstar for x = ln delta by safeguarded Newton:
+// d r*/dx = delta (r^2 + a^2)/Delta = (r^2 + a^2)/(r - r-) > 0.
+double delta_of_rstar(double rstar, double a, double M) {
+    double rp, rm;
+    horizons(a, M, rp, rm);
+    auto f = [&](double x) { return rstar_of_delta(std::exp(x), a, M) - rstar; };
+    auto fp = [&](double x) {
+        double d = std::exp(x), r = rp + d;
+        return (r * r + a * a) / (r - rm);
+    };
+    double lo = -60.0, hi = 12.0;
+    while (lo > -740.0 && f(lo) > 0.0) lo -= 60.0;
+    while (f(hi) < 0.0) hi += 12.0;
+    double x = (rstar > rp + 1.0) ? std::log(std::max(rstar - rp, 1e-300)) : 0.5 * (lo + hi);
+    x = std::min(std::max(x, lo), hi);
+    for (int it = 0; it < 200; ++it) {
+        double fx = f(x);
+        if (fx == 0.0) break;
+        if (fx < 0.0) lo = x; else hi = x;
+        double xn = x - fx / fp(x);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) <= 1e-16 * std::max(1.0, std::fabs(x))) { x = xn; break; }
+        x = xn;
+    }
+    return std::exp(x);
+}
+
+static void radial_entry(const Geometry& g, double rstar, std::vector<double>& tab, int64_t i) {
+    const double a = g.a, M = g.M;
+    const double s = g.s, m = g.m;
+    double d = delta_of_rstar(rstar, a, M);
+    double r = g.rp + d;
+    double D = d * (d + (g.rp - g.rm));
+    double w2 = r * r + a * a;
+    auto put = [&](int f, double v) { tab[(int64_t)f * g.stride + i] = v; };
+    put(R_W2, w2);
+    put(R_W4, w2 * w2);
+    put(R_A2D, a * a * D);
+    put(R_DEL, D);
+    put(R_BN, a * a * D * ((r - M) * w2 - 2.0 * r * D) / w2);
+    put(R_CTR, 2.0 * s * (r * D - M * (r * r - a * a)));
+    put(R_CTI0, 4.0 * M * a * m * r);
+    put(R_CTI1, 2.0 * s * a * D);
+    put(R_CRR, -(6.0 * w2 * D / r + 2.0 * r * D + 2.0 * s * (r - M) * w2));
+    put(R_CRI, -2.0 * m * a * w2);
+    put(R_VR, -D * (6.0 * D / (r * r) + 6.0 * (1.0 + s) * (r - M) / r));
+    put(R_VI, -(6.0 * m * a * D / r + 4.0 * s * m * a * (r - M)));
+    put(R_GR, 0.0);
+    put(R_XR, 0.0);
+}
+
+void build_geometry(Geometry& g) {
+    horizons(g.a, g.M, g.rp, g.rm);
+    g.dr = (g.rmax - g.rmin) / double(g.nr - 1);
+    g.dth = M_PI / double(g.nth);
+    g.stride = (g.nr + 63) / 64 * 64;
+    g.rad_i.assign((size_t)R_NFIELDS * g.stride, 0.0);
+    g.rad_h.assign((size_t)R_NFIELDS * g.stride, 0.0);
+    for (int64_t i = 0; i < g.nr; ++i) {
+        radial_entry(g, g.rmin + double(i) * g.dr, g.rad_i, i);
+        radial_entry(g, g.rmin + (double(i) + 0.5) * g.dr, g.rad_h, i);
+    }
+    // padding columns repeat the last node so that clamped reads stay finite
+    for (int f = 0; f < R_NFIELDS; ++f)
+        for (int64_t i = g.nr; i < g.stride; ++i) {
+            g.rad_i[(size_t)f * g.stride + i] = g.rad_i[(size_t)f * g.stride + g.nr - 1];
+            g.rad_h[(size_t)f * g.stride + i] = g.rad_h[(size_t)f * g.stride + g.nr - 1];
+        }
+    g.ang.assign((size_t)g.nth * A_STRIDE, 0.0);
+    const double h = g.dth;
+    for (int64_t j = 0; j < g.nth; ++j) {
+        double th = (double(j) + 0.5) * h;
+        double sn = std::sin(th), cs = std::cos(th);
+        double cot = cs / sn;
+        double q = g.m + g.s * cs;
+        double* A = &g.ang[(size_t)j * A_STRIDE];
+        A[A_SIN2] = sn * sn;
+        A[A_COS] = cs;
+        A[A_P] = 1.0 / (h * h) + cot / (2.0 * h);
+        A[A_M] = 1.0 / (h * h) - cot / (2.0 * h);
+        A[A_0] = -2.0 / (h * h) + (g.s - q * q / (sn * sn));
+        A[A_GTH] = 0.0;
+    }
+}
+
+void build_source(Geometry& g, double rstar0, double sr, double sth) {
+    for (int64_t i = 0; i < g.stride; ++i) {
+        int64_t k = std::min(i, g.nr - 1);
+        double xi = g.rmin + double(k) * g.dr - rstar0;
+        double xh = g.rmin + (double(k) + 0.5) * g.dr - rstar0;
+        g.rad_i[(size_t)R_GR * g.stride + i] = std::exp(-xi * xi / (2.0 * sr * sr));
+        g.rad_h[(size_t)R_GR * g.stride + i] = std::exp(-xh * xh / (2.0 * sr * sr));
+        g.rad_i[(size_t)R_XR * g.stride + i] = xi / (sr * sr);
+        g.rad_h[(size_t)R_XR * g.stride + i] = xh / (sr * sr);
+    }
+    for (int64_t j = 0; j < g.nth; ++j) {
+        double th = (double(j) + 0.5) * g.dth;
+        double d = th - 0.5 * M_PI;
+        g.ang[(size_t)j * A_STRIDE + A_GTH] = std::exp(-d * d / (2.0 * sth * sth));
+    }
+}
+
+double angular_bound(const Geometry& g) {
+    // Gershgorin: every eigenvalue of the tridiagonal angular matrix lies in a
+    // disc around a diagonal entry; the pole rows fold their ghost weight onto
+    // the diagonal with the pole sign.
+    double sig = ((std::abs(g.m + g.s) % 2) == 0) ? 1.0 : -1.0;
+    double best = 0.0;
+    for (int64_t j = 0; j < g.nth; ++j) {
+        const double* A = &g.ang[(size_t)j * A_STRIDE];
+        double diag = A[A_0], off = 0.0;
+        if (j == 0) diag += sig * A[A_M]; else off += std::fabs(A[A_M]);
+        if (j == g.nth - 1) diag += sig * A[A_P]; else off += std::fabs(A[A_P]);
+        best = std::max(best, std::fabs(diag) + off);
+    }
+    return best;
+}
+
+double max_delta_over_sigma2(const Geometry& g) {
+    double smax = 0.0;
+    for (int64_t j = 0; j < g.nth; ++j) smax = std::max(smax, g.ang[(size_t)j * A_STRIDE + A_SIN2]);
+    double best = 0.0;
+    for (const std::vector<double>* t : {&g.rad_i, &g.rad_h})
+        for (int64_t i = 0; i < g.nr; ++i) {
+            double D = (*t)[(size_t)R_DEL * g.stride + i];
+            double S2 = (*t)[(size_t)R_W4 * g.stride + i] - (*t)[(size_t)R_A2D * g.stride + i] * smax;
+            best = std::max(best, D / S2);
+        }
+    return best;
+}
+
+}  // namespace teuk

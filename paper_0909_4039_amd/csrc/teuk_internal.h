@@ -1,0 +1,110 @@
+// Internal declarations shared by the host API, the geometry builder and the
+// HIP kernels of libteuk.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/teuk.h"
+
+namespace teuk {
+
+// Radial table fields, stored structure-of-arrays: tab[f * stride + i].
+// Two tables exist: at integer nodes r*_i and at half nodes r*_{i+1/2}.
+enum RadField : int {
+    R_W2 = 0,  // w2 = r^2 + a^2
+    R_W4,      // w2^2
+    R_A2D,     // a^2 Delta
+    R_DEL,     // Delta
+    R_BN,      // a^2 Delta [(r-M) w2 - 2 r Delta] / w2   (b_* numerator / sin^2)
+    R_CTR,     // 2 s (r Delta - M (r^2 - a^2))          (c_t real numerator)
+    R_CTI0,    // 4 M a m r                               (c_t imag numerator, const)
+    R_CTI1,    // 2 s a Delta                             (c_t imag numerator, x cos)
+    R_CRR,     // -[6 w2 Delta / r + 2 r Delta + 2 s (r-M) w2]
+    R_CRI,     // -2 m a w2
+    R_VR,      // -Delta (6 Delta / r^2 + 6 (1+s)(r-M)/r)
+    R_VI,      // -[6 m a Delta / r + 4 s m a (r - M)]
+    R_GR,      // source radial Gaussian exp(-(r* - r*0)^2 / (2 sr^2))
+    R_XR,      // (r* - r*0) / sr^2   (d/dr*0 of the Gaussian's exponent)
+    R_NFIELDS
+};
+
+// Angular table fields per theta row: ang[j * A_STRIDE + f].
+enum AngField : int {
+    A_SIN2 = 0,  // sin^2 theta
+    A_COS,       // cos theta
+    A_P,         // weight of f_{j+1}: 1/h^2 + cot/(2h)
+    A_M,         // weight of f_{j-1}: 1/h^2 - cot/(2h)
+    A_0,         // weight of f_j:     -2/h^2 + s - (m + s cos)^2 / sin^2
+    A_GTH,       // source theta Gaussian
+    A_NFIELDS
+};
+constexpr int A_STRIDE = 8;
+
+struct Geometry {
+    int64_t nr = 0, nth = 0;
+    double rmin = 0, rmax = 0, dr = 0, dth = 0;
+    double a = 0, M = 1;
+    int m = 0, s = 0;
+    double rp = 0, rm = 0;
+    int64_t stride = 0;               // padded nr
+    std::vector<double> rad_i, rad_h;  // R_NFIELDS * stride each
+    std::vector<double> ang;           // nth * A_STRIDE
+};
+
+// Eq. (2): r*(delta) with delta = r - r+ and its inverse (Newton in ln delta).
+double rstar_of_delta(double delta, double a, double M);
+double delta_of_rstar(double rstar, double a, double M);
+
+// Build the radial and angular tables (source columns left at zero).
+void build_geometry(Geometry& g);
+// Fill the source columns (R_GR, R_XR, A_GTH) for a source centred at r*0.
+void build_source(Geometry& g, double rstar0, double sr, double sth);
+// Gershgorin bound of the discrete angular operator and max Delta/Sigma^2.
+double angular_bound(const Geometry& g);
+double max_delta_over_sigma2(const Geometry& g);
+
+// ------------------------------------------------------------------ kernels
+
+template <typename R>
+struct StepArgs {
+    const R* phi;      // interleaved complex [nth][nr]
+    const R* pi;
+    R* phi_out;
+    R* pi_out;
+    const R* rad_i;    // [R_NFIELDS][stride]
+    const R* rad_h;
+    const R* ang;      // [nth][A_STRIDE]
+    int64_t stride;
+    int32_t nr, nth;
+    int32_t rows;      // theta rows per wavefront tile
+    int32_t n_strips;  // r* strips of STRIP_OUT columns
+    int32_t n_chunks;  // theta chunks per strip
+    int32_t n_tiles;   // n_strips * n_chunks
+    R dt, hdt, inv_dr, ghost, amp;
+    R ph0_re, ph0_im;  // e^{-i m Omega t^n}
+    R ph1_re, ph1_im;  // e^{-i m Omega (t^n + dt/2)}
+    // waveform of the input state (row wave_row of wave), -1: off
+    R* wave;
+    int64_t wave_row;
+    int32_t iobs;
+    R alpha;
+};
+
+constexpr int WAVE = 64;
+constexpr int STRIP_OUT = WAVE - 2;   // output columns per wavefront
+constexpr int WG_WAVES = 4;
+
+void launch_step_fp64(const StepArgs<double>& a, hipStream_t s);
+void launch_step_fp32(const StepArgs<float>& a, hipStream_t s);
+void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int iobs, double alpha,
+                         hipStream_t s);
+void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs, float alpha,
+                         hipStream_t s);
+void launch_count_nonfinite_fp64(const double* x, int64_t n, unsigned int* flag, hipStream_t s);
+void launch_count_nonfinite_fp32(const float* x, int64_t n, unsigned int* flag, hipStream_t s);
+
+}  // namespace teuk

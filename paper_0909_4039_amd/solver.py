@@ -1,0 +1,134 @@
+"""Python binding of libteuk: one m-mode Teukolsky solver on one GPU.
+
+PyTorch provides the device memory (the four state tensors, the waveform
+buffer) and the stream; every step of the method runs in the library's HIP
+kernels.  Argument marshalling only.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import FP32, FP64, TeukGrid, check
+
+
+def suggest_dt(nr, nth, rstar_min, rstar_max, a, M, m, s, n_steps) -> float:
+    g = TeukGrid(nr, nth, rstar_min, rstar_max)
+    out = ctypes.c_double(0.0)
+    check(_lib.lib().teuk_suggest_dt(ctypes.byref(g), a, M, m, s, int(n_steps), ctypes.byref(out)))
+    return out.value
+
+
+def rstar_of_r(r, a, M=1.0) -> float:
+    return _lib.lib().teuk_rstar_of_r(r, a, M)
+
+
+def delta_of_rstar(rstar, a, M=1.0) -> float:
+    return _lib.lib().teuk_delta_of_rstar(rstar, a, M)
+
+
+class Solver:
+    """Lax-Wendroff evolution of (Phi, Pi) for one (a, M, m, s) mode.
+
+    State tensors are complex128 (prec=64) or complex64 (prec=32) of shape
+    (n_theta, n_rstar), r* contiguous, owned by this object and bound to the
+    library; ``phi``/``pi`` return the pair that holds the latest state.
+    """
+
+    def __init__(self, nr, nth, rstar_min, rstar_max, a, M, m, s, dt, prec=64, device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("teuk.Solver needs a GPU")
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.prec = int(prec)
+        self.dtype = torch.complex128 if self.prec == FP64 else torch.complex64
+        self.shape = (int(nth), int(nr))
+        self.params = dict(nr=nr, nth=nth, rstar_min=rstar_min, rstar_max=rstar_max, a=a, M=M, m=m, s=s, dt=dt)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self._bufs = [torch.zeros(self.shape, dtype=self.dtype, device=self.device) for _ in range(4)]
+            g = TeukGrid(nr, nth, rstar_min, rstar_max)
+            ctx = ctypes.c_void_p()
+            check(_lib.lib().teuk_create(ctypes.byref(g), a, M, m, s, dt, self.prec,
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+            self._ctx = ctx
+            check(_lib.lib().teuk_bind_state(self._ctx, *[b.data_ptr() for b in self._bufs]), self._ctx)
+        self.wave = None
+
+    # ------------------------------------------------------------ state
+    def _cur(self):
+        return check_int(_lib.lib().teuk_current(self._ctx))
+
+    @property
+    def phi(self):
+        return self._bufs[2 * self._cur()]
+
+    @property
+    def pi(self):
+        return self._bufs[2 * self._cur() + 1]
+
+    def set_state(self, phi, pi):
+        """Copy (phi, pi) into the current state buffers (on the solver's stream)."""
+        with torch.cuda.stream(self.stream):
+            self.phi.copy_(torch.as_tensor(phi).to(self.device, self.dtype))
+            self.pi.copy_(torch.as_tensor(pi).to(self.device, self.dtype))
+
+    # ------------------------------------------------------------ physics
+    def set_source(self, r0, amp, sigma_r_cells=2.0, sigma_th_cells=2.0):
+        check(_lib.lib().teuk_set_source(self._ctx, r0, amp, sigma_r_cells, sigma_th_cells), self._ctx)
+
+    def set_observer(self, rstar_obs, capacity_rows):
+        """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
+        self.wave = torch.zeros((int(capacity_rows), self.shape[0]), dtype=self.dtype, device=self.device)
+        check(_lib.lib().teuk_set_observer(self._ctx, rstar_obs, self.wave.data_ptr(), int(capacity_rows)),
+              self._ctx)
+        return self.wave
+
+    def clear_observer(self):
+        check(_lib.lib().teuk_set_observer(self._ctx, 0.0, None, 0), self._ctx)
+        self.wave = None
+
+    def step(self, n):
+        check(_lib.lib().teuk_step(self._ctx, int(n)), self._ctx)
+
+    def extract(self, rstar_obs):
+        out = torch.empty((self.shape[0],), dtype=self.dtype, device=self.device)
+        check(_lib.lib().teuk_extract(self._ctx, rstar_obs, out.data_ptr()), self._ctx)
+        return out
+
+    def get_time(self):
+        t = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(_lib.lib().teuk_get_time(self._ctx, ctypes.byref(t), ctypes.byref(n)), self._ctx)
+        return t.value, n.value
+
+    def set_time(self, t, step):
+        check(_lib.lib().teuk_set_time(self._ctx, float(t), int(step)), self._ctx)
+
+    def set_tiling(self, rows_per_wave):
+        check(_lib.lib().teuk_set_tiling(self._ctx, int(rows_per_wave)), self._ctx)
+
+    def check_finite(self):
+        """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""
+        check(_lib.lib().teuk_check_finite(self._ctx), self._ctx)
+
+    def status(self):
+        return _lib.lib().teuk_status(self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.lib().teuk_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def check_int(v):
+    if v < 0:
+        raise _lib.TeukError(v)
+    return v

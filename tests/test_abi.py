@@ -1,0 +1,96 @@
+"""CPU-side checks of libteuk: the C ABI loads, exports what include/teuk.h
+declares, validates arguments, and its host geometry agrees with the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "teuk.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(teuk_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0909_4039_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libteuk.so is not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_bindings_cover_header():
+    from paper_0909_4039_amd import _lib
+    missing = [n for n in declared_functions() if n not in _lib._SIGS]
+    assert not missing, missing
+
+
+def test_strerror(L):
+    from paper_0909_4039_amd import _lib
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.teuk_strerror(code).decode().startswith("TEUK_")
+    assert b"unknown" in L.teuk_strerror(-99)
+
+
+def test_create_rejects_bad_arguments(L):
+    from paper_0909_4039_amd._lib import TeukGrid, EINVAL
+    ctx = ctypes.c_void_p()
+    good = TeukGrid(64, 16, -50.0, 150.0)
+    bad_grids = [TeukGrid(3, 16, -50.0, 150.0), TeukGrid(64, 3, -50.0, 150.0), TeukGrid(64, 16, 10.0, 10.0)]
+    for g in bad_grids:
+        assert L.teuk_create(ctypes.byref(g), 0.5, 1.0, 2, -2, 0.01, 64, None, ctypes.byref(ctx)) == EINVAL
+        assert not ctx.value
+    cases = [(1.0, 1.0, 2, -2, 0.01, 64),    # a = M
+             (-0.1, 1.0, 2, -2, 0.01, 64),   # a < 0
+             (0.5, 0.0, 2, -2, 0.01, 64),    # M = 0
+             (0.5, 1.0, 2, -3, 0.01, 64),    # |s| > 2
+             (0.5, 1.0, 2, -2, 0.0, 64),     # dt = 0
+             (0.5, 1.0, 2, -2, float("nan"), 64),
+             (0.5, 1.0, 2, -2, 0.01, 16)]    # precision
+    for a, M, m, s, dt, prec in cases:
+        assert L.teuk_create(ctypes.byref(good), a, M, m, s, dt, prec, None, ctypes.byref(ctx)) == EINVAL
+    assert L.teuk_create(None, 0.5, 1.0, 2, -2, 0.01, 64, None, ctypes.byref(ctx)) == EINVAL
+    assert L.teuk_create(ctypes.byref(good), 0.5, 1.0, 2, -2, 0.01, 64, None, None) == EINVAL
+
+
+def test_null_context_calls(L):
+    from paper_0909_4039_amd._lib import EINVAL
+    assert L.teuk_step(None, 1) == EINVAL
+    assert L.teuk_destroy(None) == EINVAL
+    assert L.teuk_status(None) == EINVAL
+    assert L.teuk_current(None) == EINVAL
+    assert L.teuk_extract(None, 1.0, None) == EINVAL
+
+
+@pytest.mark.parametrize("a", [0.0, 0.3, 0.9, 0.99])
+def test_host_geometry_matches_oracle(L, oracle_mod, a):
+    # same Eq. (2), independent code: bisection (oracle) vs Newton (library)
+    for rs in (-100.0, -10.0, 0.0, 12.5, 100.0, 400.0):
+        d1 = L.teuk_delta_of_rstar(rs, a, 1.0)
+        d2 = oracle_mod.delta_of_rstar(rs, a, 1.0)
+        assert d1 == pytest.approx(d2, rel=1e-13)
+    for r in (2.5, 6.0, 10.0, 80.0):
+        assert L.teuk_rstar_of_r(r, a, 1.0) == pytest.approx(oracle_mod.rstar_of_r(r, a, 1.0), rel=1e-14, abs=1e-13)
+
+
+@pytest.mark.parametrize("cfg", [(256, 64, -50.0, 150.0, 0.0, 2, 2000),
+                                 (8192, 256, -100.0, 400.0, 0.9, 2, 50000),
+                                 (512, 128, -100.0, 400.0, 0.6, 3, 1000)])
+def test_suggested_dt_is_conservative(L, oracle_mod, cfg):
+    from paper_0909_4039_amd.solver import suggest_dt
+    nr, nth, r0, r1, a, m, n = cfg
+    mine = suggest_dt(nr, nth, r0, r1, a, 1.0, m, -2, n)
+    ref = oracle_mod.stable_dt(nr, nth, r0, r1, a, 1.0, m, -2, n)
+    assert 0.5 * ref < mine <= ref * (1 + 1e-12)
