@@ -5,7 +5,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libteuk.so")
+# TEUK_LIB selects another build of the same ABI (e.g. an installed copy).
+LIB_PATH = os.environ.get("TEUK_LIB") or os.path.join(HERE, "libteuk.so")
 
 OK, EINVAL, ESTATE, EDEVICE, EUNSTABLE, ENOTSUP = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 64, 32

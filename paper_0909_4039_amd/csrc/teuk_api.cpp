@@ -108,7 +108,7 @@ bool observer_index(const Geometry& g, double rstar_obs, int& i0, double& alpha)
 int validate_phys(const teuk_grid* g, double a, double M, int32_t s) {
     if (!g) return TEUK_EINVAL;
     if (g->n_rstar < 4 || g->n_theta < 4) return TEUK_EINVAL;
-    if (g->n_rstar > (int64_t)1 << 30 || g->n_theta > (int64_t)1 << 20) return TEUK_EINVAL;
+    if (g->n_rstar > (int64_t)1 << 26 || g->n_theta > (int64_t)1 << 20) return TEUK_EINVAL;
     if ((int64_t)g->n_rstar * g->n_theta > ((int64_t)1 << 40)) return TEUK_EINVAL;
     if (!(g->rstar_min < g->rstar_max) || !std::isfinite(g->rstar_min) || !std::isfinite(g->rstar_max))
         return TEUK_EINVAL;
@@ -134,8 +134,7 @@ int launch_steps(teuk_ctx* c, int64_t n) {
     a.dt = (R)c->dt;
     a.hdt = (R)(0.5 * c->dt);
     a.inv_dr = (R)(1.0 / g.dr);
-    a.ghost = (R)((std::abs(g.m + g.s) % 2 == 0) ? 1.0 : -1.0);
-    a.amp = (R)(c->has_src ? c->amp : 0.0);
+    a.m2ma = (R)(-2.0 * g.m * g.a);
     a.wave = (R*)c->wave;
     a.iobs = c->iobs;
     a.alpha = (R)c->alpha;
@@ -259,7 +258,7 @@ int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, do
     c->rstar0 = rstar_of_delta(r0 - g.rp, g.a, g.M);
     c->Omega = std::sqrt(g.M) / (std::pow(r0, 1.5) + g.a * std::sqrt(g.M));
     c->has_src = true;
-    build_source(g, c->rstar0, sigma_r_cells * g.dr, sigma_th_cells * g.dth);
+    build_source(g, c->rstar0, sigma_r_cells * g.dr, sigma_th_cells * g.dth, amp);
     return upload_tables(c);
 }
 

@@ -63,15 +63,11 @@ static void radial_entry(const Geometry& g, double rstar, std::vector<double>& t
     double w2 = r * r + a * a;
     auto put = [&](int f, double v) { tab[(int64_t)f * g.stride + i] = v; };
     put(R_W2, w2);
-    put(R_W4, w2 * w2);
-    put(R_A2D, a * a * D);
     put(R_DEL, D);
-    put(R_BN, a * a * D * ((r - M) * w2 - 2.0 * r * D) / w2);
+    put(R_WBN, a * a * D * ((r - M) * w2 - 2.0 * r * D));
     put(R_CTR, 2.0 * s * (r * D - M * (r * r - a * a)));
     put(R_CTI0, 4.0 * M * a * m * r);
-    put(R_CTI1, 2.0 * s * a * D);
     put(R_CRR, -(6.0 * w2 * D / r + 2.0 * r * D + 2.0 * s * (r - M) * w2));
-    put(R_CRI, -2.0 * m * a * w2);
     put(R_VR, -D * (6.0 * D / (r * r) + 6.0 * (1.0 + s) * (r - M) / r));
     put(R_VI, -(6.0 * m * a * D / r + 4.0 * s * m * a * (r - M)));
     put(R_GR, 0.0);
@@ -97,6 +93,7 @@ void build_geometry(Geometry& g) {
         }
     g.ang.assign((size_t)g.nth * A_STRIDE, 0.0);
     const double h = g.dth;
+    const double sig = ((std::abs(g.m + g.s) % 2) == 0) ? 1.0 : -1.0;
     for (int64_t j = 0; j < g.nth; ++j) {
         double th = (double(j) + 0.5) * h;
         double sn = std::sin(th), cs = std::cos(th);
@@ -104,15 +101,23 @@ void build_geometry(Geometry& g) {
         double q = g.m + g.s * cs;
         double* A = &g.ang[(size_t)j * A_STRIDE];
         A[A_SIN2] = sn * sn;
-        A[A_COS] = cs;
-        A[A_P] = 1.0 / (h * h) + cot / (2.0 * h);
-        A[A_M] = 1.0 / (h * h) - cot / (2.0 * h);
-        A[A_0] = -2.0 / (h * h) + (g.s - q * q / (sn * sn));
+        A[A_A2S2] = g.a * g.a * sn * sn;
+        A[A_CS] = 2.0 * g.s * g.a * cs;
+        double wp = 1.0 / (h * h) + cot / (2.0 * h);
+        double wm = 1.0 / (h * h) - cot / (2.0 * h);
+        double w0 = -2.0 / (h * h) + (g.s - q * q / (sn * sn));
+        // pole ghosts: f_{-1} = sig f_0, f_{nth} = sig f_{nth-1}
+        if (j == 0) { w0 += sig * wm; wm = 0.0; }
+        if (j == g.nth - 1) { w0 += sig * wp; wp = 0.0; }
+        A[A_P] = wp;
+        A[A_M] = wm;
+        A[A_0] = w0;
         A[A_GTH] = 0.0;
+        A[A_AGTH] = 0.0;
     }
 }
 
-void build_source(Geometry& g, double rstar0, double sr, double sth) {
+void build_source(Geometry& g, double rstar0, double sr, double sth, double amp) {
     for (int64_t i = 0; i < g.stride; ++i) {
         int64_t k = std::min(i, g.nr - 1);
         double xi = g.rmin + double(k) * g.dr - rstar0;
@@ -125,22 +130,19 @@ void build_source(Geometry& g, double rstar0, double sr, double sth) {
     for (int64_t j = 0; j < g.nth; ++j) {
         double th = (double(j) + 0.5) * g.dth;
         double d = th - 0.5 * M_PI;
-        g.ang[(size_t)j * A_STRIDE + A_GTH] = std::exp(-d * d / (2.0 * sth * sth));
+        double gth = std::exp(-d * d / (2.0 * sth * sth));
+        g.ang[(size_t)j * A_STRIDE + A_GTH] = gth;
+        g.ang[(size_t)j * A_STRIDE + A_AGTH] = amp * gth;
     }
 }
 
 double angular_bound(const Geometry& g) {
-    // Gershgorin: every eigenvalue of the tridiagonal angular matrix lies in a
-    // disc around a diagonal entry; the pole rows fold their ghost weight onto
-    // the diagonal with the pole sign.
-    double sig = ((std::abs(g.m + g.s) % 2) == 0) ? 1.0 : -1.0;
+    // Gershgorin: every eigenvalue of the tridiagonal angular matrix lies in
+    // a disc around a diagonal entry (pole ghosts are already folded in).
     double best = 0.0;
     for (int64_t j = 0; j < g.nth; ++j) {
         const double* A = &g.ang[(size_t)j * A_STRIDE];
-        double diag = A[A_0], off = 0.0;
-        if (j == 0) diag += sig * A[A_M]; else off += std::fabs(A[A_M]);
-        if (j == g.nth - 1) diag += sig * A[A_P]; else off += std::fabs(A[A_P]);
-        best = std::max(best, std::fabs(diag) + off);
+        best = std::max(best, std::fabs(A[A_0]) + std::fabs(A[A_P]) + std::fabs(A[A_M]));
     }
     return best;
 }
@@ -152,8 +154,8 @@ double max_delta_over_sigma2(const Geometry& g) {
     for (const std::vector<double>* t : {&g.rad_i, &g.rad_h})
         for (int64_t i = 0; i < g.nr; ++i) {
             double D = (*t)[(size_t)R_DEL * g.stride + i];
-            double S2 = (*t)[(size_t)R_W4 * g.stride + i] - (*t)[(size_t)R_A2D * g.stride + i] * smax;
-            best = std::max(best, D / S2);
+            double w2 = (*t)[(size_t)R_W2 * g.stride + i];
+            best = std::max(best, D / (w2 * w2 - g.a * g.a * D * smax));
         }
     return best;
 }

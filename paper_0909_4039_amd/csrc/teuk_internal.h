@@ -14,32 +14,33 @@ namespace teuk {
 
 // Radial table fields, stored structure-of-arrays: tab[f * stride + i].
 // Two tables exist: at integer nodes r*_i and at half nodes r*_{i+1/2}.
+// With w2 = r^2 + a^2, every coefficient of S (Eq. 12) is a radial field
+// times at most one angular factor, all over Sigma^2 = w2^2 - a^2 Delta sin^2.
 enum RadField : int {
-    R_W2 = 0,  // w2 = r^2 + a^2
-    R_W4,      // w2^2
-    R_A2D,     // a^2 Delta
+    R_W2 = 0,  // w2
     R_DEL,     // Delta
-    R_BN,      // a^2 Delta [(r-M) w2 - 2 r Delta] / w2   (b_* numerator / sin^2)
-    R_CTR,     // 2 s (r Delta - M (r^2 - a^2))          (c_t real numerator)
-    R_CTI0,    // 4 M a m r                               (c_t imag numerator, const)
-    R_CTI1,    // 2 s a Delta                             (c_t imag numerator, x cos)
-    R_CRR,     // -[6 w2 Delta / r + 2 r Delta + 2 s (r-M) w2]
-    R_CRI,     // -2 m a w2
-    R_VR,      // -Delta (6 Delta / r^2 + 6 (1+s)(r-M)/r)
-    R_VI,      // -[6 m a Delta / r + 4 s m a (r - M)]
+    R_WBN,     // a^2 Delta [(r-M) w2 - 2 r Delta]       (b b_* = WBN sin^2 / Sigma^4)
+    R_CTR,     // 2 s (r Delta - M (r^2 - a^2))          (Sigma^2 Re c_t)
+    R_CTI0,    // 4 M a m r                              (Sigma^2 Im c_t = CTI0 + 2 s a cos Delta)
+    R_CRR,     // -[6 w2 Delta / r + 2 r Delta + 2 s (r-M) w2]   (Sigma^2 Re c_r; Im c_r = -2 m a w2)
+    R_VR,      // -Delta (6 Delta / r^2 + 6 (1+s)(r-M)/r)        (Sigma^2 Re V)
+    R_VI,      // -[6 m a Delta / r + 4 s m a (r - M)]           (Sigma^2 Im V)
     R_GR,      // source radial Gaussian exp(-(r* - r*0)^2 / (2 sr^2))
     R_XR,      // (r* - r*0) / sr^2   (d/dr*0 of the Gaussian's exponent)
     R_NFIELDS
 };
 
-// Angular table fields per theta row: ang[j * A_STRIDE + f].
+// Angular table fields per theta row: ang[j * A_STRIDE + f].  The pole
+// rows fold the ghost cell (mirror with sign (-1)^|m+s|) into their weights.
 enum AngField : int {
     A_SIN2 = 0,  // sin^2 theta
-    A_COS,       // cos theta
-    A_P,         // weight of f_{j+1}: 1/h^2 + cot/(2h)
-    A_M,         // weight of f_{j-1}: 1/h^2 - cot/(2h)
-    A_0,         // weight of f_j:     -2/h^2 + s - (m + s cos)^2 / sin^2
+    A_A2S2,      // a^2 sin^2 theta
+    A_CS,        // 2 s a cos theta
+    A_P,         // weight of f_{j+1}: 1/h^2 + cot/(2h)        (0 on the last row)
+    A_M,         // weight of f_{j-1}: 1/h^2 - cot/(2h)        (0 on the first row)
+    A_0,         // weight of f_j: -2/h^2 + s - (m + s cos)^2 / sin^2 (+ folded ghost)
     A_GTH,       // source theta Gaussian
+    A_AGTH,      // amp x source theta Gaussian
     A_NFIELDS
 };
 constexpr int A_STRIDE = 8;
@@ -62,7 +63,7 @@ double delta_of_rstar(double rstar, double a, double M);
 // Build the radial and angular tables (source columns left at zero).
 void build_geometry(Geometry& g);
 // Fill the source columns (R_GR, R_XR, A_GTH) for a source centred at r*0.
-void build_source(Geometry& g, double rstar0, double sr, double sth);
+void build_source(Geometry& g, double rstar0, double sr, double sth, double amp);
 // Gershgorin bound of the discrete angular operator and max Delta/Sigma^2.
 double angular_bound(const Geometry& g);
 double max_delta_over_sigma2(const Geometry& g);
@@ -84,7 +85,8 @@ struct StepArgs {
     int32_t n_strips;  // r* strips of STRIP_OUT columns
     int32_t n_chunks;  // theta chunks per strip
     int32_t n_tiles;   // n_strips * n_chunks
-    R dt, hdt, inv_dr, ghost, amp;
+    R dt, hdt, inv_dr;
+    R m2ma;            // -2 m a  (Sigma^2 Im c_r = m2ma w2)
     R ph0_re, ph0_im;  // e^{-i m Omega t^n}
     R ph1_re, ph1_im;  // e^{-i m Omega (t^n + dt/2)}
     // waveform of the input state (row wave_row of wave), -1: off
