@@ -22,6 +22,24 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 BYTES_PER_UPDATE = {64: 64, 32: 32}   # read (Phi, Pi) + write (Phi', Pi'), complex
+KERNEL_SRC = os.path.join(ROOT, "paper_0909_4039_amd", "csrc", "teuk_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_traffic.json")
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they
+    were taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernel_sha256") != h:
+            return None
+        e = rec["fp%d" % prec]
+        return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],
+                "write_bytes": e["write_bytes"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -114,7 +132,7 @@ def main():
                    "a": W.a, "m": W.m, "s": W.s, "r0": W.r0, "rstar_obs": W.rstar_obs, "dt": dt,
                    "initial_data": "zero, source on"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK, "traffic": measured_traffic(64),
                      "kernel": "lw_step_kernel<double>",
                      "bytes_per_launch": BYTES_PER_UPDATE[64] * pts},
     }

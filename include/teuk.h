@@ -110,9 +110,20 @@ int teuk_set_time(teuk_ctx* ctx, double t, int64_t step);
  * negative: error code. */
 int teuk_current(teuk_ctx* ctx);
 
-/* Tile shape of the step kernel: rows_per_wave theta rows per wavefront
- * (1..4096).  0 restores the default. */
-int teuk_set_tiling(teuk_ctx* ctx, int32_t rows_per_wave);
+/* Tile shape of the step kernel (performance only; results are bitwise
+ * identical for every choice): rows_per_wave theta rows per wavefront
+ * (1..4096; 0 restores the default and ignores order) and the block order
+ * (0: theta-chunk-major, 1: r*-strip-group-major). */
+int teuk_set_tiling(teuk_ctx* ctx, int32_t rows_per_wave, int32_t order);
+int teuk_get_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* order);
+
+/* Temporal blocking: fuse steps_per_launch (1 or 2) Lax-Wendroff steps in
+ * one kernel launch, keeping the intermediate state on chip (performance
+ * only: results are bitwise identical to single steps; an odd remainder of
+ * teuk_step(n) runs as a single step).  teuk_get_blocking returns the
+ * current setting or a negative error code. */
+int teuk_set_blocking(teuk_ctx* ctx, int32_t steps_per_launch);
+int teuk_get_blocking(teuk_ctx* ctx);
 
 /* Scan the current state for non-finite values (synchronous).  Returns
  * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */

@@ -39,7 +39,10 @@ _SIGS = {
     "teuk_get_time": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "teuk_set_time": (ctypes.c_int, [_P, _D, _I64]),
     "teuk_current": (ctypes.c_int, [_P]),
-    "teuk_set_tiling": (ctypes.c_int, [_P, _I32]),
+    "teuk_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "teuk_get_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "teuk_set_blocking": (ctypes.c_int, [_P, _I32]),
+    "teuk_get_blocking": (ctypes.c_int, [_P]),
     "teuk_check_finite": (ctypes.c_int, [_P]),
     "teuk_status": (ctypes.c_int, [_P]),
     "teuk_last_error": (ctypes.c_char_p, [_P]),

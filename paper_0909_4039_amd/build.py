@@ -15,6 +15,8 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: the kernels write each FMA out
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
 ]
 

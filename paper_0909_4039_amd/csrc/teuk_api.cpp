@@ -40,6 +40,8 @@ struct teuk_ctx {
     int64_t step0 = 0, step = 0;
     // tiling
     int rows = 0;
+    int order = 0;
+    int kblock = 1;   // steps fused per launch
     // errors
     int status = TEUK_OK;
     char err[512] = {0};
@@ -67,14 +69,12 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
 size_t elem_size(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
 
 int default_rows(int nr, int nth) {
-    // enough wavefronts to fill 256 CUs several times over, with chunks
-    // tall enough that the 4-row halo stays a small fraction of the reads
-    int strips = (nr + STRIP_OUT - 1) / STRIP_OUT;
-    int64_t want = 4096;
-    int rows = (int)std::max<int64_t>(1, (int64_t)strips * nth / want);
-    int p = 16;
-    while (p * 2 <= rows) p *= 2;
-    return std::min(std::max(p, 16), std::max(nth, 1));
+    // Short chunks give many wavefronts per strip group (several rounds of
+    // the 256 CUs, so the tail of the last round is small); the 4-row halo
+    // of each chunk is re-read, mostly from L2.  Measured on 32768 x 1024:
+    // 16-32 rows are best for FP64 and FP32.
+    (void)nr;
+    return std::min(16, std::max(nth, 1));
 }
 
 int upload_tables(teuk_ctx* c) {
@@ -128,9 +128,8 @@ int launch_steps(teuk_ctx* c, int64_t n) {
     a.nr = (int)g.nr;
     a.nth = (int)g.nth;
     a.rows = c->rows;
-    a.n_strips = (int)((g.nr + STRIP_OUT - 1) / STRIP_OUT);
     a.n_chunks = (int)((g.nth + c->rows - 1) / c->rows);
-    a.n_tiles = a.n_strips * a.n_chunks;
+    a.order = c->order;
     a.dt = (R)c->dt;
     a.hdt = (R)(0.5 * c->dt);
     a.inv_dr = (R)(1.0 / g.dr);
@@ -138,24 +137,32 @@ int launch_steps(teuk_ctx* c, int64_t n) {
     a.wave = (R*)c->wave;
     a.iobs = c->iobs;
     a.alpha = (R)c->alpha;
-    for (int64_t k = 0; k < n; ++k) {
-        double t = c->t0 + double(c->step - c->step0) * c->dt;
-        double w0 = g.m * c->Omega * t, w1 = g.m * c->Omega * (t + 0.5 * c->dt);
-        a.ph0_re = (R)std::cos(w0);
-        a.ph0_im = (R)(-std::sin(w0));
-        a.ph1_re = (R)std::cos(w1);
-        a.ph1_im = (R)(-std::sin(w1));
+    for (int64_t done = 0; done < n;) {
+        const int kb = (c->kblock >= 2 && n - done >= 2) ? 2 : 1;
+        const int so = WAVE - 2 * kb;   // valid output columns per strip
+        a.kb = kb;
+        a.n_strips = (int)((g.nr + so - 1) / so);
+        a.n_tiles = a.n_strips * a.n_chunks;
+        for (int q = 0; q < KB_MAX; ++q) {
+            double t = c->t0 + double(c->step + q - c->step0) * c->dt;
+            double w0 = g.m * c->Omega * t, w1 = g.m * c->Omega * (t + 0.5 * c->dt);
+            a.ph[2 * q][0] = (R)std::cos(w0);
+            a.ph[2 * q][1] = (R)(-std::sin(w0));
+            a.ph[2 * q + 1][0] = (R)std::cos(w1);
+            a.ph[2 * q + 1][1] = (R)(-std::sin(w1));
+            int64_t row = c->step + q - c->obs_step0;
+            a.wave_row[q] = (q < kb && c->wave && row >= 0 && row < c->wave_cap) ? row : -1;
+        }
         a.phi = (const R*)c->buf[c->cur][0];
         a.pi = (const R*)c->buf[c->cur][1];
         a.phi_out = (R*)c->buf[1 - c->cur][0];
         a.pi_out = (R*)c->buf[1 - c->cur][1];
-        int64_t row = c->step - c->obs_step0;
-        a.wave_row = (c->wave && row >= 0 && row < c->wave_cap) ? row : -1;
         if constexpr (std::is_same<R, double>::value) launch_step_fp64(a, c->stream);
         else launch_step_fp32(a, c->stream);
         HIP_TRY(c, hipGetLastError());
         c->cur = 1 - c->cur;
-        c->step += 1;
+        c->step += kb;
+        done += kb;
     }
     // the last state's waveform row
     int64_t row = c->step - c->obs_step0;
@@ -331,14 +338,34 @@ int teuk_current(teuk_ctx* c) {
     return c->cur;
 }
 
-int teuk_set_tiling(teuk_ctx* c, int32_t rows_per_wave) {
+int teuk_set_tiling(teuk_ctx* c, int32_t rows_per_wave, int32_t order) {
     if (!c) return TEUK_EINVAL;
+    if (order < 0 || order > 1) return fail(c, TEUK_EINVAL, "order must be 0 or 1");
     if (rows_per_wave == 0) {
         c->rows = default_rows((int)c->geo.nr, (int)c->geo.nth);
+        c->order = 0;
         return TEUK_OK;
     }
     if (rows_per_wave < 1 || rows_per_wave > 4096) return fail(c, TEUK_EINVAL, "rows_per_wave out of range");
     c->rows = rows_per_wave;
+    c->order = order;
+    return TEUK_OK;
+}
+
+int teuk_set_blocking(teuk_ctx* c, int32_t steps_per_launch) {
+    if (!c) return TEUK_EINVAL;
+    if (steps_per_launch < 1 || steps_per_launch > KB_MAX)
+        return fail(c, TEUK_EINVAL, "steps_per_launch must be 1..%d", KB_MAX);
+    c->kblock = steps_per_launch;
+    return TEUK_OK;
+}
+
+int teuk_get_blocking(teuk_ctx* c) { return c ? c->kblock : TEUK_EINVAL; }
+
+int teuk_get_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* order) {
+    if (!c) return TEUK_EINVAL;
+    if (rows_per_wave) *rows_per_wave = c->rows;
+    if (order) *order = c->order;
     return TEUK_OK;
 }
 

@@ -70,6 +70,8 @@ double max_delta_over_sigma2(const Geometry& g);
 
 // ------------------------------------------------------------------ kernels
 
+constexpr int KB_MAX = 2;   // steps fused per launch (temporal blocking)
+
 template <typename R>
 struct StepArgs {
     const R* phi;      // interleaved complex [nth][nr]
@@ -82,22 +84,23 @@ struct StepArgs {
     int64_t stride;
     int32_t nr, nth;
     int32_t rows;      // theta rows per wavefront tile
-    int32_t n_strips;  // r* strips of STRIP_OUT columns
+    int32_t n_strips;  // r* strips of (64 - 2 kb) output columns
     int32_t n_chunks;  // theta chunks per strip
     int32_t n_tiles;   // n_strips * n_chunks
+    int32_t order;     // block order: 0 chunk-major, 1 strip-group-major
+    int32_t kb;        // steps in this launch (1 or 2)
     R dt, hdt, inv_dr;
     R m2ma;            // -2 m a  (Sigma^2 Im c_r = m2ma w2)
-    R ph0_re, ph0_im;  // e^{-i m Omega t^n}
-    R ph1_re, ph1_im;  // e^{-i m Omega (t^n + dt/2)}
-    // waveform of the input state (row wave_row of wave), -1: off
+    // per fused step k: e^{-i m Omega t^{n+k}} and e^{-i m Omega (t^{n+k} + dt/2)}
+    R ph[2 * KB_MAX][2];
+    // waveform rows of the states entering each fused step (-1: not recorded)
     R* wave;
-    int64_t wave_row;
+    int64_t wave_row[KB_MAX];
     int32_t iobs;
     R alpha;
 };
 
 constexpr int WAVE = 64;
-constexpr int STRIP_OUT = WAVE - 2;   // output columns per wavefront
 constexpr int WG_WAVES = 4;
 
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s);

@@ -40,9 +40,28 @@ template <typename R>
 __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename R>
 __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+// The library is compiled without implicit multiply-add contraction; every
+// fused multiply-add below is written out, so that the rounding of each
+// point is the same whatever code surrounds it (tile shape, temporal
+// blocking, batching).
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+}
+// a b + c
+template <typename R>
+__device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c) {
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+// real s times complex a plus c
+template <typename R>
+__device__ __forceinline__ cx<R> rfma(R s, cx<R> a, cx<R> c) {
+    return {fma(s, a.re, c.re), fma(s, a.im, c.im)};
+}
+// three-point angular stencil wp f+ + wm f- + w0 f0
+template <typename R>
+__device__ __forceinline__ cx<R> stencil(R wp, cx<R> fp, R wm, cx<R> fm, R w0, cx<R> f0) {
+    return rfma(wp, fp, rfma(wm, fm, w0 * f0));
 }
 
 template <typename R> struct vec2;
@@ -235,7 +254,7 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2
     cx<R> CR = {fma(q.wbn * g.sin2, y2, q.crr), m2ma * q.w2};
     cx<R> CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
     cx<R> V = {q.vr, q.vi};
-    cx<R> acc = cmul(CR, df) + cmul(V, f) + cmul(CT, X);
+    cx<R> acc = cfma(CR, df, cfma(V, f, cmul(CT, X)));
     cx<R> T = (g.agth * q.gr) * ph;
     Stage<R> o;
     o.phi = {fma(tau, X.re, f0.re), fma(tau, X.im, f0.im)};
@@ -245,26 +264,154 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2
     return o;
 }
 
+// State of one Lax-Wendroff step marching upwards through theta (one
+// pipeline stage).  Rings are indexed by (row - first row) mod 3, resolved at
+// compile time by the three-way unrolled loop of the kernel.
 template <typename R>
+struct Pipe {
+    cx<R> pb[3];    // Phi means at half points c+1/2, time n        (rows L-2..L)
+    cx<R> phh[3];   // Phi means at integer points c, time n+1/2      (rows L-3..L-1)
+    // Each stage is split into its angular part, which needs the next row,
+    // and the rest.  Pending (non-angular) parts:
+    cx<R> hP, hQp;  // predictor of half row L-1: final Phi, partial Pi
+    R hD;           // (dt/2) Delta/Sigma^2 at that half row
+    cx<R> nQp;      // corrector of row L-2: partial Pi
+    R nD;           // dt Delta/Sigma^2 at that row
+    cx<R> up, uq;   // input row L-1 (the u^n term of the corrector)
+    int olo, ohi;   // rows [olo, ohi) whose outputs this stage produces
+    int ihi;        // input rows end at ihi (they start at olo - 2, clipped at 0)
+    int plo, phi;   // half rows [plo, phi] of the predictor
+};
+
+template <typename R>
+__device__ __forceinline__ void pipe_init(Pipe<R>& st, int olo, int ohi, int nth) {
+    const cx<R> zero = {R(0), R(0)};
+    for (int k = 0; k < 3; ++k) { st.pb[k] = zero; st.phh[k] = zero; }
+    st.hP = zero; st.hQp = zero; st.hD = R(0); st.nQp = zero; st.nD = R(0);
+    st.up = zero; st.uq = zero;
+    st.olo = olo; st.ohi = ohi;
+    st.ihi = min(ohi + 2, nth);
+    st.plo = max(olo - 1, 0);
+    st.phi = min(ohi, nth - 1);
+}
+
+// Wavefront-uniform constants shared by the stages.
+template <typename R>
+struct Consts {
+    const R* ang;
+    const R (*srad)[N_RAD_USED][WAVE];
+    int lane, nth;
+    R keep, idr, dt, hdt, m2ma;
+};
+
+// One iteration of a stage at its row index L with input row L = (p, q).
+// Returns the stage's finished outputs: Phi at row L-1 (okP) and Pi at row
+// L-2 (okQ).  The four parts of the iteration sit behind wave-uniform
+// branches, which also keep the scheduler from stretching live ranges.
+template <int S0, typename R>
+__device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L, cx<R> p, cx<R> q,
+                                          cx<R> ph0, cx<R> ph1, R* wave, int64_t wrow, int wl, int rlo,
+                                          int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
+    constexpr int S1 = (S0 + 2) % 3;   // slot of row L-1
+    constexpr int S2 = (S0 + 1) % 3;   // slot of row L-2 (and L-3 -> S0 for phh)
+    const R half = R(0.5);
+    const int P = L - 1, Q = L - 2;
+    const cx<R> up = st.up, uq = st.uq;
+    st.up = p;
+    st.uq = q;
+    // ---- A1: input row L; half-point mean and compact differences at c+1/2
+    cx<R> Qb, dP, dQ;   // set when row L exists; read only by A2, which implies it
+    if (L < st.ihi) {
+        cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
+        st.pb[S0] = half * (p + p1);
+        Qb = half * (q + q1);
+        dP = K.idr * (p1 - p);
+        dQ = K.idr * (q1 - q);
+        if (wrow >= 0 && L >= rlo && L < rhi) {
+            if (K.lane == wl) stc(wave, wrow * K.nth + L, rfma(alpha, p1, (R(1) - alpha) * p));
+        }
+    }
+    // ---- B1: finish the predictor (Eq. 13) of half row P and form the
+    //      corrector's means and differences at c (time n+1/2)
+    cx<R> Qh, dhP, dhQ;  // set by B1; read only by B2, whose rows are a subset
+    if (P >= st.plo && P <= st.phi) {
+        const R* ag = K.ang + (int64_t)P * A_STRIDE;
+        const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
+        cx<R> Lf = stencil(wp, st.pb[S0], wm, st.pb[S2], w0, st.pb[S1]);
+        cx<R> hQ = rfma(st.hD, Lf, st.hQp);
+        cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
+        st.phh[S1] = half * (st.hP + hPm);
+        Qh = half * (hQ + hQm);
+        dhP = K.idr * (st.hP - hPm);
+        dhQ = K.idr * (hQ - hQm);
+    }
+    // ---- A2: non-angular part of the predictor of half row L
+    if (L >= st.plo && L <= st.phi) {
+        const Ang<R> g = load_ang(K.ang, L);
+        const Rad<R> qh = lds_rad<R>(K.srad[0], K.lane);   // half point c+1/2
+        Stage<R> o = stage(qh, g, K.m2ma, K.hdt, ph0, st.pb[S0], Qb, st.pb[S0], Qb, dP, dQ);
+        st.hP = o.phi;
+        st.hQp = o.pi_part;
+        st.hD = o.dw;
+    }
+    // ---- C: finish the corrector (Eq. 14) of row Q: its Pi
+    okQ = (Q >= st.olo && Q < st.ohi);
+    if (okQ) {
+        const R* ag = K.ang + (int64_t)Q * A_STRIDE;
+        const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
+        cx<R> Lf = stencil(wp, st.phh[S1], wm, st.phh[S0], w0, st.phh[S2]);
+        outQ = K.keep * rfma(st.nD, Lf, st.nQp);
+    }
+    // ---- B2: non-angular part of the corrector of row P; its Phi is final
+    okP = (P >= st.olo && P < st.ohi);
+    if (okP) {
+        const Ang<R> g = load_ang(K.ang, P);
+        const Rad<R> qi = lds_rad<R>(K.srad[1], K.lane);   // integer point c
+        Stage<R> o = stage(qi, g, K.m2ma, K.dt, ph1, up, uq, st.phh[S1], Qh, dhP, dhQ);
+        st.nQp = o.pi_part;
+        st.nD = o.dw;
+        outP = K.keep * o.phi;
+    }
+}
+
+// KB Lax-Wendroff steps per launch (temporal blocking).  Stage k advances
+// u^{n+k} to u^{n+k+1}; the intermediate states never leave registers:
+// stage k+1 consumes row X of stage k's output once both its Phi (finished
+// one iteration earlier) and its Pi are final, two rows behind.  Each
+// stage's arithmetic per point is the same code as for KB = 1, so results
+// are bitwise identical to KB single steps.  A strip loses one valid column
+// per side and a chunk needs two more halo rows per side for each extra
+// stage.
+template <typename R, int KB>
 __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi, const R* __restrict__ pi,
                                                     R* __restrict__ phi_out, R* __restrict__ pi_out,
                                                     const R* __restrict__ rad_i, const R* __restrict__ rad_h,
                                                     const R* __restrict__ ang, R* __restrict__ wave,
                                                     StepArgs<R> A) {
+    constexpr int SO = WAVE - 2 * KB;   // valid output columns per strip
     const int lane = threadIdx.x & (WAVE - 1);
     // wave-uniform quantities: keep them in scalar registers
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     // A workgroup = WG_WAVES adjacent r* strips at the same theta chunk, so
     // that every row access of the group is one contiguous 4 KiB (FP64)
-    // span; blocks run chunk-major so that concurrent groups on an XCD also
-    // touch neighbouring columns of the same rows.
+    // span.  Block order (a tuning choice): chunk-major lets the groups that
+    // run together on an XCD touch neighbouring columns of the same rows;
+    // group-major keeps a strip group's chunks together so their halo rows
+    // are served by L2.
     const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int chunk = blk / ngrp;
-    const int strip = (blk - chunk * ngrp) * WG_WAVES + wid;
+    int chunk, grp;
+    if (A.order == 0) {  // chunk-major: concurrent groups read the same rows
+        chunk = blk / ngrp;
+        grp = blk - chunk * ngrp;
+    } else {             // group-major: adjacent chunks share their halo rows in L2
+        grp = blk / A.n_chunks;
+        chunk = blk - grp * A.n_chunks;
+    }
+    const int strip = grp * WG_WAVES + wid;
     if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
     const int nr = A.nr, nth = A.nth;
-    const int c = strip * STRIP_OUT - 1 + lane;
+    const int c = strip * SO - KB + lane;
     // Lanes outside the grid read a clamped column: they feed only the
     // half points beyond the r* boundaries, whose outputs are the Dirichlet
     // zeros or are never stored.
@@ -279,110 +426,68 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     }
     const int j0 = chunk * A.rows;
     const int jend = min(j0 + A.rows, nth);
-    const bool out_lane = (c >= 0) && (c < nr) && lane >= 1 && lane <= WAVE - 2;
-    const R keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
+    const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
     const unsigned boff = cu * (unsigned)(2 * sizeof(R));          // byte offset of this lane's column
     const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(R));
-    const R dt = A.dt, hdt = A.hdt, idr = A.inv_dr, m2ma = A.m2ma;
-    const cx<R> ph0 = {A.ph0_re, A.ph0_im}, ph1 = {A.ph1_re, A.ph1_im};
-    const R half = R(0.5);
+    Consts<R> K;
+    K.ang = ang;
+    K.srad = srad;
+    K.lane = lane;
+    K.nth = nth;
+    K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
+    K.idr = A.inv_dr;
+    K.dt = A.dt;
+    K.hdt = A.hdt;
+    K.m2ma = A.m2ma;
+    // recorder: the strip holding columns iobs and iobs+1 among its lanes
+    const bool rec = (A.iobs / SO == strip);
+    const int wl = A.iobs - strip * SO + KB;
     const cx<R> zero = {R(0), R(0)};
-    const bool rec = (A.wave_row >= 0) && (A.iobs / STRIP_OUT == strip);
-    const int wl = A.iobs - strip * STRIP_OUT + 1;
 
-    // Rings indexed by (row - Ls) mod 3, resolved at compile time by the
-    // three-way unrolled loop below.
-    cx<R> pb[3] = {zero, zero, zero};  // Phi at half points, time n   (rows L-2..L)
-    cx<R> phh[3] = {zero, zero, zero}; // Phi at integer points, time n+1/2 (rows L-3..L-1)
-    // Each stage is split into its angular part, which needs the next row,
-    // and the rest.  Pending (non-angular) parts:
-    cx<R> hP = zero, hQp = zero;  // predictor of half row L-1: final Phi, partial Pi
-    R hD = R(0);                  // (dt/2) Delta/Sigma^2 at that half row
-    cx<R> nQp = zero;             // corrector of row L-2: partial Pi
-    R nD = R(0);                  // dt Delta/Sigma^2 at that row
+    // stage k produces rows [j0 - 2(KB-1-k), jend + 2(KB-1-k)), clipped
+    Pipe<R> st[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        pipe_init(st[k], max(j0 - 2 * (KB - 1 - k), 0), min(jend + 2 * (KB - 1 - k), nth), nth);
+    const int Ls = max(st[0].olo - 2, 0);          // first input row of stage 0
+    const int Le = jend - 1 + 2 * KB;             // last iteration: the last stage's C at row jend-1
+    cx<R> held[KB];                               // Phi of stage k's output row L-1, kept one iteration
+#pragma unroll
+    for (int k = 0; k < KB; ++k) held[k] = zero;
 
-    const int Ls = max(j0 - 2, 0);
-    const int Le = min(j0 + A.rows + 1, nth + 1);
-    const int Plo = max(j0 - 1, 0), Phi_ = min(j0 + A.rows, nth - 1);
-    // prefetch ring, indexed like the other rings (row Ls is always inside
-    // the grid; row Ls+1 too unless the grid has a single row chunk edge)
+    // prefetched input row of stage 0 (row Ls is always inside the grid)
     cx<R> pf_p = ld_row_once(phi, (int64_t)Ls * nr, boff), pf_q = ld_row_once(pi, (int64_t)Ls * nr, boff);
-    cx<R> u_p = zero, u_q = zero;   // u^n of the previous row
 
-    // Every stage sits behind a wave-uniform branch; the branches also keep
-    // the scheduler from stretching live ranges across stages.
     auto iter = [&](auto PHC, int L) {
         constexpr int S0 = decltype(PHC)::value;   // slot of row L
-        constexpr int S1 = (S0 + 2) % 3;          // slot of row L-1
-        constexpr int S2 = (S0 + 1) % 3;          // slot of row L-2 (and L-3 -> S0 for phh)
         if (L > Le) return;
-        const int P = L - 1, Q = L - 2;
-        // Rows L and L+1 were requested by earlier iterations; request row
-        // L+2 now into the slot that row L-1 used.  Row P = L-1 stays in
-        // registers for the corrector (B2): re-reading it would miss in L2
-        // at full occupancy and double the HBM read traffic.
-        const cx<R> up = u_p, uq = u_q;
+        // Row L was requested by the previous iteration; request row L+1 now.
         cx<R> p = pf_p, q = pf_q;
-        u_p = p;
-        u_q = q;
-        if (L + 1 < nth && L + 1 <= Le) {
+        if (L + 1 < st[0].ihi && L + 1 <= Le) {
             const int64_t row = (int64_t)(L + 1) * nr;
             pf_p = ld_row_once(phi, row, boff);
             pf_q = ld_row_once(pi, row, boff);
         }
         __builtin_amdgcn_sched_barrier(0);
-        // ---- A1: row L; half-point mean and compact differences at c+1/2
-        cx<R> Qb, dP, dQ;   // set when row L exists; read only by A2, which implies it
-        if (L < nth) {
-            cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
-            pb[S0] = half * (p + p1);
-            Qb = half * (q + q1);
-            dP = idr * (p1 - p);
-            dQ = idr * (q1 - q);
-            if (rec && L >= j0 && L < jend) {
-                if (lane == wl) stc(wave, A.wave_row * nth + L, (R(1) - A.alpha) * p + A.alpha * p1);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int Lk = L - 2 * k;   // stage k works two rows behind stage k-1
+            cx<R> oP, oQ;
+            bool okP, okQ;
+            const cx<R> ph0 = {A.ph[2 * k][0], A.ph[2 * k][1]};
+            const cx<R> ph1 = {A.ph[2 * k + 1][0], A.ph[2 * k + 1][1]};
+            pipe_iter<S0>(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row[k] : -1, wl, j0, jend,
+                          A.alpha, oP, okP, oQ, okQ);
+            if (k == KB - 1) {
+                if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, oQ);
+                if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, oP);
+            } else {
+                // next stage's input row Lk-2: Phi finished one iteration ago,
+                // Pi finished now
+                p = held[k];
+                q = oQ;
+                if (okP) held[k] = oP;
             }
-        }
-        // ---- B1: finish the predictor (Eq. 13) of half row P and form the
-        //      corrector's means and differences at c (time n+1/2)
-        cx<R> Qh, dhP, dhQ;  // set by B1; read only by B2, whose rows are a subset
-        if (P >= Plo && P <= Phi_) {
-            const R* ag = ang + (int64_t)P * A_STRIDE;
-            const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
-            cx<R> Lf = wp * pb[S0] + wm * pb[S2] + w0 * pb[S1];
-            cx<R> hQ = hQp + hD * Lf;
-            cx<R> hPm = shfl_up1(hP), hQm = shfl_up1(hQ);
-            phh[S1] = half * (hP + hPm);
-            Qh = half * (hQ + hQm);
-            dhP = idr * (hP - hPm);
-            dhQ = idr * (hQ - hQm);
-        }
-        // ---- A2: non-angular part of the predictor of half row L
-        if (L >= Plo && L <= Phi_) {
-            const Ang<R> g = load_ang(ang, L);
-            const Rad<R> qh = lds_rad<R>(srad[0], lane);   // half point c+1/2
-            Stage<R> o = stage(qh, g, m2ma, hdt, ph0, pb[S0], Qb, pb[S0], Qb, dP, dQ);
-            hP = o.phi;
-            hQp = o.pi_part;
-            hD = o.dw;
-        }
-        // ---- C: finish the corrector (Eq. 14) of row Q; store its Pi
-        if (Q >= j0 && Q < jend) {
-            const R* ag = ang + (int64_t)Q * A_STRIDE;
-            const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
-            cx<R> Lf = wp * phh[S1] + wm * phh[S0] + w0 * phh[S2];
-            cx<R> nQ = keep * (nQp + nD * Lf);
-            if (out_lane) st_row(pi_out, (int64_t)Q * nr, soff, nQ);
-        }
-        // ---- B2: non-angular part of the corrector of row P; its Phi is final
-        if (P >= j0 && P < jend) {
-            const Ang<R> g = load_ang(ang, P);
-            const int64_t row = (int64_t)P * nr;
-            const Rad<R> qi = lds_rad<R>(srad[1], lane);   // integer point c
-            Stage<R> o = stage(qi, g, m2ma, dt, ph1, up, uq, phh[S1], Qh, dhP, dhQ);
-            nQp = o.pi_part;
-            nD = o.dw;
-            if (out_lane) st_row(phi_out, row, soff, keep * o.phi);
         }
     };
     using I0 = std::integral_constant<int, 0>;
@@ -398,8 +503,12 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
 template <typename R>
 static void launch_step(const StepArgs<R>& a, hipStream_t s) {
     int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
-    hipLaunchKernelGGL(lw_step_kernel<R>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.phi, a.pi, a.phi_out,
-                       a.pi_out, a.rad_i, a.rad_h, a.ang, a.wave, a);
+    if (a.kb == 2)
+        hipLaunchKernelGGL((lw_step_kernel<R, 2>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.phi, a.pi,
+                           a.phi_out, a.pi_out, a.rad_i, a.rad_h, a.ang, a.wave, a);
+    else
+        hipLaunchKernelGGL((lw_step_kernel<R, 1>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.phi, a.pi,
+                           a.phi_out, a.pi_out, a.rad_i, a.rad_h, a.ang, a.wave, a);
 }
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step(a, s); }
 void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step(a, s); }
@@ -412,7 +521,7 @@ __global__ void extract_kernel(const R* __restrict__ phi, R* __restrict__ out, i
     if (j >= nth) return;
     cx<R> p0 = ldc(phi, (int64_t)j * nr + i0);
     cx<R> p1 = ldc(phi, (int64_t)j * nr + i0 + 1);
-    stc(out, j, (R(1) - alpha) * p0 + alpha * p1);
+    stc(out, j, rfma(alpha, p1, (R(1) - alpha) * p0));
 }
 void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int iobs, double alpha,
                          hipStream_t s) {

@@ -106,8 +106,21 @@ class Solver:
     def set_time(self, t, step):
         check(_lib.lib().teuk_set_time(self._ctx, float(t), int(step)), self._ctx)
 
-    def set_tiling(self, rows_per_wave):
-        check(_lib.lib().teuk_set_tiling(self._ctx, int(rows_per_wave)), self._ctx)
+    def set_tiling(self, rows_per_wave, order=0):
+        check(_lib.lib().teuk_set_tiling(self._ctx, int(rows_per_wave), int(order)), self._ctx)
+
+    def set_blocking(self, steps_per_launch):
+        """Fuse 1 or 2 steps per kernel launch (bitwise identical results)."""
+        check(_lib.lib().teuk_set_blocking(self._ctx, int(steps_per_launch)), self._ctx)
+
+    def get_blocking(self):
+        return check_int(_lib.lib().teuk_get_blocking(self._ctx))
+
+    def get_tiling(self):
+        r = ctypes.c_int32()
+        o = ctypes.c_int32()
+        check(_lib.lib().teuk_get_tiling(self._ctx, ctypes.byref(r), ctypes.byref(o)), self._ctx)
+        return r.value, o.value
 
     def check_finite(self):
         """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""

@@ -20,13 +20,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(case, phi, pi, n, prec=64, rows=None, dt=None):
+def run_gpu(case, phi, pi, n, prec=64, rows=None, dt=None, order=0, kb=1):
     import torch
     from paper_0909_4039_amd.solver import Solver
     s = Solver(case["nr"], case["nth"], case["rmin"], case["rmax"], case["a"], 1.0, case["m"], case["s"],
                dt if dt is not None else case["dt"], prec=prec)
     if rows:
-        s.set_tiling(rows)
+        s.set_tiling(rows, order)
+    if kb != 1:
+        s.set_blocking(kb)
     if case.get("amp", 0.0) != 0.0 or case.get("r0"):
         s.set_source(case.get("r0", 10.0), case.get("amp", 0.0))
     s.set_state(phi, pi)
@@ -85,10 +87,37 @@ def test_tiling_bitwise_invariant(oracle_mod):
     print("[gpu] tiling invariance", flush=True)
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=3)
     ref = run_gpu(case, phi, pi, 20, rows=1)
-    for rows in (2, 3, 7, 16, 64, 4096):
-        got = run_gpu(case, phi, pi, 20, rows=rows)
+    for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1)):
+        got = run_gpu(case, phi, pi, 20, rows=rows, order=order)
         for x, y in zip(got, ref):
-            assert np.array_equal(x, y), rows
+            assert np.array_equal(x, y), (rows, order)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("idx", [0, 1, 3, 4, 6])
+def test_temporal_blocking_bitwise(oracle_mod, idx, prec):
+    # two steps per launch reproduce single steps bit for bit (odd step
+    # counts end with a single step; the recorder sees every state)
+    case = dict(SMALL[idx])
+    case["dt"] = _dt(oracle_mod, case)
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=40 + idx)
+    for n, rows in ((21, None), (8, 5), (3, 64)):
+        ref = run_gpu(case, phi, pi, n, prec=prec, rows=rows)
+        got = run_gpu(case, phi, pi, n, prec=prec, rows=rows, kb=2)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), (case["name"], n, rows)
+
+
+@pytest.mark.parametrize("robs_index", [59, 60, 61, 119, 120])
+def test_blocked_observer_on_strip_boundaries(oracle_mod, robs_index):
+    # with two steps per launch the strips are 60 columns wide
+    case = dict(name="obs2", nr=250, nth=12, rmin=0.0, rmax=249.0, a=0.6, m=2, s=-2, r0=20.0, amp=1.0)
+    case["robs"] = robs_index + 0.61
+    case["dt"] = _dt(oracle_mod, case)
+    phi, pi = inputs.random_state(250, 12, seed=robs_index)
+    gp, gq, gw = run_gpu(case, phi, pi, 14, kb=2)
+    op, oq, ow = run_oracle(oracle_mod, case, phi, pi, 14)
+    assert rel(gw, ow) <= TOL64 and rel(gp, op) <= TOL64
 
 
 def test_schwarzschild_pulse_256x64(oracle_mod):
