@@ -4,9 +4,14 @@
 A bench "step" is one time step of the whole hot path over the full grid:
 predictor and corrector (paper Eqs. 13-14) with the coefficients of
 Eqs. (5)-(12), the particle source, the boundary conditions and the
-waveform recorder, all in the library's fused kernel.  The workload is the
+waveform recorder, all in the library's fused kernel (by default two steps
+per launch, bitwise identical to single steps).  The workload is the
 largest single-mode grid: a = 0.99, m = 2, s = -2, source at r0 = 8,
 32768 x 1024 (r*, theta) points, zero initial data.  Prints one JSON line.
+
+Roofline: the algorithmic traffic of one launch is one read of u^n and one
+write of u^{n+k} (64 B per grid point in FP64, 32 B in FP32) whatever the
+number k of fused steps; it is divided by the launch's average duration.
 """
 from __future__ import annotations
 
@@ -59,6 +64,8 @@ def time_solver(W, prec, steps, warmup):
     dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
     s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
     s.set_source(W.r0, W.amp)
+    kb = s.get_blocking()
+    tiling = s.get_tiling()
     s.set_observer(W.rstar_obs, warmup + steps + 1)
     s.step(warmup)
     torch.cuda.synchronize()
@@ -71,9 +78,8 @@ def time_solver(W, prec, steps, warmup):
     torch.cuda.synchronize()
     s.check_finite()
     ms = e0.elapsed_time(e1)
-    rows = s.params
     s.close()
-    return ms, dt
+    return ms, dt, kb, tiling
 
 
 def cpu_baseline(W, seconds):
@@ -111,10 +117,11 @@ def main():
     from paper_0909_4039_amd import workloads
     W = workloads.LARGE
     pts = W.nr * W.nth
-    ms, dt = time_solver(W, 64, args.steps, args.warmup)
+    ms, dt, kb, tiling = time_solver(W, 64, args.steps, args.warmup)
     ms_step = ms / args.steps
     ups = pts * args.steps / (ms * 1e-3)
-    achieved = BYTES_PER_UPDATE[64] * pts / (ms_step * 1e-3)
+    launch_s = ms_step * kb * 1e-3               # average duration of one launch (kb steps)
+    achieved = BYTES_PER_UPDATE[64] * pts / launch_s
     out = {
         "metric": "grid-point updates/s FP64/FP32 + % HBM roofline; batched vs per-mode; adjoint/fwd",
         "value": ups,
@@ -130,17 +137,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.name, "n_rstar": W.nr, "n_theta": W.nth, "rstar": [W.rstar_min, W.rstar_max],
                    "a": W.a, "m": W.m, "s": W.s, "r0": W.r0, "rstar_obs": W.rstar_obs, "dt": dt,
-                   "initial_data": "zero, source on"},
+                   "initial_data": "zero, source on", "steps_per_launch": kb,
+                   "rows_per_wave": tiling[0]},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": measured_traffic(64),
-                     "kernel": "lw_step_kernel<double>",
-                     "bytes_per_launch": BYTES_PER_UPDATE[64] * pts},
+                     "kernel": f"lw_step_kernel<double, {kb}>",
+                     "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
+        # update rate expressed as the bandwidth an unblocked step would need
+        "effective": {"update_bandwidth_GBs": BYTES_PER_UPDATE[64] * ups / 1e9,
+                      "frac_of_hbm_peak": BYTES_PER_UPDATE[64] * ups / HBM_PEAK},
     }
     if not args.no_fp32:
-        ms32, _ = time_solver(W, 32, args.steps, args.warmup)
+        ms32, _, kb32, _ = time_solver(W, 32, args.steps, args.warmup)
         ups32 = pts * args.steps / (ms32 * 1e-3)
-        out["fp32"] = {"value": ups32, "ms_per_step": ms32 / args.steps,
-                       "hbm_frac": BYTES_PER_UPDATE[32] * pts / (ms32 / args.steps * 1e-3) / HBM_PEAK}
+        l32 = ms32 / args.steps * kb32 * 1e-3
+        out["fp32"] = {"value": ups32, "unit": "grid-point updates/s", "ms_per_step": ms32 / args.steps,
+                       "steps_per_launch": kb32,
+                       "hbm_frac_per_launch": BYTES_PER_UPDATE[32] * pts / l32 / HBM_PEAK,
+                       "effective_frac": BYTES_PER_UPDATE[32] * ups32 / HBM_PEAK,
+                       "traffic": measured_traffic(32)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -117,11 +117,11 @@ int teuk_current(teuk_ctx* ctx);
 int teuk_set_tiling(teuk_ctx* ctx, int32_t rows_per_wave, int32_t order);
 int teuk_get_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* order);
 
-/* Temporal blocking: fuse steps_per_launch (1 or 2) Lax-Wendroff steps in
- * one kernel launch, keeping the intermediate state on chip (performance
- * only: results are bitwise identical to single steps; an odd remainder of
- * teuk_step(n) runs as a single step).  teuk_get_blocking returns the
- * current setting or a negative error code. */
+/* Temporal blocking: fuse steps_per_launch (1 or 2; default 2) Lax-Wendroff
+ * steps in one kernel launch, keeping the intermediate state on chip
+ * (performance only: results are bitwise identical to single steps; an odd
+ * remainder of teuk_step(n) runs as a single step).  teuk_get_blocking
+ * returns the current setting or a negative error code. */
 int teuk_set_blocking(teuk_ctx* ctx, int32_t steps_per_launch);
 int teuk_get_blocking(teuk_ctx* ctx);
 

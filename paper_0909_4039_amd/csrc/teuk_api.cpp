@@ -41,7 +41,8 @@ struct teuk_ctx {
     // tiling
     int rows = 0;
     int order = 0;
-    int kblock = 1;   // steps fused per launch
+    int kblock = 2;   // steps fused per launch
+    bool rows_default = true;   // rows follow kblock until set explicitly
     // errors
     int status = TEUK_OK;
     char err[512] = {0};
@@ -68,13 +69,12 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
 
 size_t elem_size(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
 
-int default_rows(int nr, int nth) {
-    // Short chunks give many wavefronts per strip group (several rounds of
-    // the 256 CUs, so the tail of the last round is small); the 4-row halo
-    // of each chunk is re-read, mostly from L2.  Measured on 32768 x 1024:
-    // 16-32 rows are best for FP64 and FP32.
-    (void)nr;
-    return std::min(16, std::max(nth, 1));
+int default_rows(int nth, int kblock, int prec) {
+    // Measured on 32768 x 1024: single steps prefer short chunks (16 rows:
+    // many wavefronts, small tail); two fused steps need 4 halo rows per
+    // side and prefer 64 (FP32) to 96 (FP64) rows.
+    int rows = (kblock >= 2) ? (prec == 64 ? 96 : 64) : 16;
+    return std::min(rows, std::max(nth, 1));
 }
 
 int upload_tables(teuk_ctx* c) {
@@ -205,7 +205,7 @@ int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, do
     geo.m = m;
     geo.s = s;
     build_geometry(geo);
-    c->rows = default_rows((int)geo.nr, (int)geo.nth);
+    c->rows = default_rows((int)geo.nth, c->kblock, prec);
     size_t es = elem_size(prec);
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipMalloc(&c->d_rad_i, geo.rad_i.size() * es) != hipSuccess ||
@@ -342,12 +342,14 @@ int teuk_set_tiling(teuk_ctx* c, int32_t rows_per_wave, int32_t order) {
     if (!c) return TEUK_EINVAL;
     if (order < 0 || order > 1) return fail(c, TEUK_EINVAL, "order must be 0 or 1");
     if (rows_per_wave == 0) {
-        c->rows = default_rows((int)c->geo.nr, (int)c->geo.nth);
+        c->rows = default_rows((int)c->geo.nth, c->kblock, c->prec);
         c->order = 0;
+        c->rows_default = true;
         return TEUK_OK;
     }
     if (rows_per_wave < 1 || rows_per_wave > 4096) return fail(c, TEUK_EINVAL, "rows_per_wave out of range");
     c->rows = rows_per_wave;
+    c->rows_default = false;
     c->order = order;
     return TEUK_OK;
 }
@@ -357,6 +359,7 @@ int teuk_set_blocking(teuk_ctx* c, int32_t steps_per_launch) {
     if (steps_per_launch < 1 || steps_per_launch > KB_MAX)
         return fail(c, TEUK_EINVAL, "steps_per_launch must be 1..%d", KB_MAX);
     c->kblock = steps_per_launch;
+    if (c->rows_default) c->rows = default_rows((int)c->geo.nth, c->kblock, c->prec);
     return TEUK_OK;
 }
 

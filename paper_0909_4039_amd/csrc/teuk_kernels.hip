@@ -265,14 +265,18 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2
 }
 
 // State of one Lax-Wendroff step marching upwards through theta (one
-// pipeline stage).  Rings are indexed by (row - first row) mod 3, resolved at
-// compile time by the three-way unrolled loop of the kernel.
+// pipeline stage).  The three-point angular stencil of each stage,
+// wp f(j+1) + (wm f(j-1) + w0 f(j)), is formed in two parts: the bracket as
+// soon as row j is known, the wp term one row later.  Only one previous row
+// and one partial sum per stage are carried.
 template <typename R>
 struct Pipe {
-    cx<R> pb[3];    // Phi means at half points c+1/2, time n        (rows L-2..L)
-    cx<R> phh[3];   // Phi means at integer points c, time n+1/2      (rows L-3..L-1)
-    // Each stage is split into its angular part, which needs the next row,
-    // and the rest.  Pending (non-angular) parts:
+    cx<R> pb_prev;  // Phi mean at half point c+1/2, time n, row L-1
+    cx<R> pb_acc;   // bracket of the predictor's stencil for half row L-1
+    cx<R> ph_prev;  // Phi mean at integer point c, time n+1/2, row L-2
+    cx<R> ph_acc;   // bracket of the corrector's stencil for row L-2
+    // Each Lax-Wendroff stage is split into its angular part, which needs the
+    // next row, and the rest.  Pending (non-angular) parts:
     cx<R> hP, hQp;  // predictor of half row L-1: final Phi, partial Pi
     R hD;           // (dt/2) Delta/Sigma^2 at that half row
     cx<R> nQp;      // corrector of row L-2: partial Pi
@@ -286,7 +290,7 @@ struct Pipe {
 template <typename R>
 __device__ __forceinline__ void pipe_init(Pipe<R>& st, int olo, int ohi, int nth) {
     const cx<R> zero = {R(0), R(0)};
-    for (int k = 0; k < 3; ++k) { st.pb[k] = zero; st.phh[k] = zero; }
+    st.pb_prev = zero; st.pb_acc = zero; st.ph_prev = zero; st.ph_acc = zero;
     st.hP = zero; st.hQp = zero; st.hD = R(0); st.nQp = zero; st.nD = R(0);
     st.up = zero; st.uq = zero;
     st.olo = olo; st.ohi = ohi;
@@ -306,24 +310,24 @@ struct Consts {
 
 // One iteration of a stage at its row index L with input row L = (p, q).
 // Returns the stage's finished outputs: Phi at row L-1 (okP) and Pi at row
-// L-2 (okQ).  The four parts of the iteration sit behind wave-uniform
-// branches, which also keep the scheduler from stretching live ranges.
-template <int S0, typename R>
+// L-2 (okQ).  The parts of the iteration sit behind wave-uniform branches,
+// which also keep the scheduler from stretching live ranges.
+template <typename R>
 __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L, cx<R> p, cx<R> q,
                                           cx<R> ph0, cx<R> ph1, R* wave, int64_t wrow, int wl, int rlo,
                                           int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
-    constexpr int S1 = (S0 + 2) % 3;   // slot of row L-1
-    constexpr int S2 = (S0 + 1) % 3;   // slot of row L-2 (and L-3 -> S0 for phh)
     const R half = R(0.5);
+    const cx<R> zero = {R(0), R(0)};
     const int P = L - 1, Q = L - 2;
     const cx<R> up = st.up, uq = st.uq;
     st.up = p;
     st.uq = q;
     // ---- A1: input row L; half-point mean and compact differences at c+1/2
-    cx<R> Qb, dP, dQ;   // set when row L exists; read only by A2, which implies it
+    // (rows past the grid keep a zero mean: they meet only zero weights)
+    cx<R> pbL = zero, Qb, dP, dQ;   // Qb, dP, dQ are read only by A2, which implies A1 ran
     if (L < st.ihi) {
         cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
-        st.pb[S0] = half * (p + p1);
+        pbL = half * (p + p1);
         Qb = half * (q + q1);
         dP = K.idr * (p1 - p);
         dQ = K.idr * (q1 - q);
@@ -333,45 +337,49 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     }
     // ---- B1: finish the predictor (Eq. 13) of half row P and form the
     //      corrector's means and differences at c (time n+1/2)
-    cx<R> Qh, dhP, dhQ;  // set by B1; read only by B2, whose rows are a subset
+    cx<R> phL = zero, Qh, dhP, dhQ;  // Qh, dhP, dhQ are read only by B2, whose rows are a subset
     if (P >= st.plo && P <= st.phi) {
-        const R* ag = K.ang + (int64_t)P * A_STRIDE;
-        const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
-        cx<R> Lf = stencil(wp, st.pb[S0], wm, st.pb[S2], w0, st.pb[S1]);
+        const R wp = K.ang[(int64_t)P * A_STRIDE + A_P];
+        cx<R> Lf = rfma(wp, pbL, st.pb_acc);
         cx<R> hQ = rfma(st.hD, Lf, st.hQp);
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
-        st.phh[S1] = half * (st.hP + hPm);
+        phL = half * (st.hP + hPm);
         Qh = half * (hQ + hQm);
         dhP = K.idr * (st.hP - hPm);
         dhQ = K.idr * (hQ - hQm);
     }
-    // ---- A2: non-angular part of the predictor of half row L
+    // ---- A2: non-angular part of the predictor of half row L and the
+    //      bracket of its stencil
     if (L >= st.plo && L <= st.phi) {
         const Ang<R> g = load_ang(K.ang, L);
         const Rad<R> qh = lds_rad<R>(K.srad[0], K.lane);   // half point c+1/2
-        Stage<R> o = stage(qh, g, K.m2ma, K.hdt, ph0, st.pb[S0], Qb, st.pb[S0], Qb, dP, dQ);
+        Stage<R> o = stage(qh, g, K.m2ma, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
         st.hP = o.phi;
         st.hQp = o.pi_part;
         st.hD = o.dw;
+        st.pb_acc = rfma(g.wm, st.pb_prev, g.w0 * pbL);
     }
+    st.pb_prev = pbL;
     // ---- C: finish the corrector (Eq. 14) of row Q: its Pi
     okQ = (Q >= st.olo && Q < st.ohi);
     if (okQ) {
-        const R* ag = K.ang + (int64_t)Q * A_STRIDE;
-        const R wp = ag[A_P], wm = ag[A_M], w0 = ag[A_0];
-        cx<R> Lf = stencil(wp, st.phh[S1], wm, st.phh[S0], w0, st.phh[S2]);
+        const R wp = K.ang[(int64_t)Q * A_STRIDE + A_P];
+        cx<R> Lf = rfma(wp, phL, st.ph_acc);
         outQ = K.keep * rfma(st.nD, Lf, st.nQp);
     }
-    // ---- B2: non-angular part of the corrector of row P; its Phi is final
+    // ---- B2: non-angular part of the corrector of row P (its Phi is final)
+    //      and the bracket of its stencil
     okP = (P >= st.olo && P < st.ohi);
     if (okP) {
         const Ang<R> g = load_ang(K.ang, P);
         const Rad<R> qi = lds_rad<R>(K.srad[1], K.lane);   // integer point c
-        Stage<R> o = stage(qi, g, K.m2ma, K.dt, ph1, up, uq, st.phh[S1], Qh, dhP, dhQ);
+        Stage<R> o = stage(qi, g, K.m2ma, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
         st.nQp = o.pi_part;
         st.nD = o.dw;
         outP = K.keep * o.phi;
+        st.ph_acc = rfma(g.wm, st.ph_prev, g.w0 * phL);
     }
+    st.ph_prev = phL;
 }
 
 // KB Lax-Wendroff steps per launch (temporal blocking).  Stage k advances
@@ -458,8 +466,7 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     // prefetched input row of stage 0 (row Ls is always inside the grid)
     cx<R> pf_p = ld_row_once(phi, (int64_t)Ls * nr, boff), pf_q = ld_row_once(pi, (int64_t)Ls * nr, boff);
 
-    auto iter = [&](auto PHC, int L) {
-        constexpr int S0 = decltype(PHC)::value;   // slot of row L
+    auto iter = [&](int L) {
         if (L > Le) return;
         // Row L was requested by the previous iteration; request row L+1 now.
         cx<R> p = pf_p, q = pf_q;
@@ -476,8 +483,8 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
             bool okP, okQ;
             const cx<R> ph0 = {A.ph[2 * k][0], A.ph[2 * k][1]};
             const cx<R> ph1 = {A.ph[2 * k + 1][0], A.ph[2 * k + 1][1]};
-            pipe_iter<S0>(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row[k] : -1, wl, j0, jend,
-                          A.alpha, oP, okP, oQ, okQ);
+            pipe_iter(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row[k] : -1, wl, j0, jend, A.alpha, oP,
+                      okP, oQ, okQ);
             if (k == KB - 1) {
                 if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, oQ);
                 if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, oP);
@@ -490,13 +497,10 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
             }
         }
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    for (int L = Ls; L <= Le; L += 3) {
-        iter(I0{}, L);
-        iter(I1{}, L + 1);
-        iter(I2{}, L + 2);
+    // unrolled twice so that the carried values alternate between register sets
+    for (int L = Ls; L <= Le; L += 2) {
+        iter(L);
+        iter(L + 1);
     }
 }
 

@@ -20,14 +20,14 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_gpu(case, phi, pi, n, prec=64, rows=None, dt=None, order=0, kb=1):
+def run_gpu(case, phi, pi, n, prec=64, rows=None, dt=None, order=0, kb=None):
     import torch
     from paper_0909_4039_amd.solver import Solver
     s = Solver(case["nr"], case["nth"], case["rmin"], case["rmax"], case["a"], 1.0, case["m"], case["s"],
                dt if dt is not None else case["dt"], prec=prec)
     if rows:
         s.set_tiling(rows, order)
-    if kb != 1:
+    if kb is not None:            # None: the library default (two steps per launch)
         s.set_blocking(kb)
     if case.get("amp", 0.0) != 0.0 or case.get("r0"):
         s.set_source(case.get("r0", 10.0), case.get("amp", 0.0))
@@ -68,12 +68,13 @@ def _dt(oracle_mod, c, nsteps=None):
                                 nsteps or 10000)
 
 
+@pytest.mark.parametrize("kb", [1, 2])
 @pytest.mark.parametrize("case", SMALL, ids=[c["name"] for c in SMALL])
-def test_parity_random_data(oracle_mod, case):
+def test_parity_random_data(oracle_mod, case, kb):
     case = dict(case, dt=_dt(oracle_mod, case))
-    print(f"[gpu] parity {case['name']} n={case['n']}", flush=True)
-    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=hash(case["name"]) % 1000)
-    gp, gq, gw = run_gpu(case, phi, pi, case["n"])
+    print(f"[gpu] parity {case['name']} n={case['n']} kb={kb}", flush=True)
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=sum(map(ord, case["name"])) % 1000)
+    gp, gq, gw = run_gpu(case, phi, pi, case["n"], kb=kb)
     op, oq, ow = run_oracle(oracle_mod, case, phi, pi, case["n"])
     assert rel(gp, op) <= TOL64 and rel(gq, oq) <= TOL64, (rel(gp, op), rel(gq, oq))
     assert rel(gw, ow) <= TOL64, rel(gw, ow)
@@ -86,11 +87,12 @@ def test_tiling_bitwise_invariant(oracle_mod):
     case["dt"] = _dt(oracle_mod, case)
     print("[gpu] tiling invariance", flush=True)
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=3)
-    ref = run_gpu(case, phi, pi, 20, rows=1)
-    for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1)):
-        got = run_gpu(case, phi, pi, 20, rows=rows, order=order)
-        for x, y in zip(got, ref):
-            assert np.array_equal(x, y), (rows, order)
+    for kb in (1, 2):
+        ref = run_gpu(case, phi, pi, 20, rows=1, kb=kb)
+        for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1)):
+            got = run_gpu(case, phi, pi, 20, rows=rows, order=order, kb=kb)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), (rows, order, kb)
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -102,7 +104,7 @@ def test_temporal_blocking_bitwise(oracle_mod, idx, prec):
     case["dt"] = _dt(oracle_mod, case)
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=40 + idx)
     for n, rows in ((21, None), (8, 5), (3, 64)):
-        ref = run_gpu(case, phi, pi, n, prec=prec, rows=rows)
+        ref = run_gpu(case, phi, pi, n, prec=prec, rows=rows, kb=1)
         got = run_gpu(case, phi, pi, n, prec=prec, rows=rows, kb=2)
         for x, y in zip(got, ref):
             assert np.array_equal(x, y), (case["name"], n, rows)
@@ -181,7 +183,7 @@ def test_observer_on_strip_boundaries(oracle_mod, robs_index):
     case["robs"] = robs_index + 0.37
     case["dt"] = _dt(oracle_mod, case)
     phi, pi = inputs.random_state(250, 12, seed=robs_index)
-    gp, gq, gw = run_gpu(case, phi, pi, 15)
+    gp, gq, gw = run_gpu(case, phi, pi, 15, kb=1)
     op, oq, ow = run_oracle(oracle_mod, case, phi, pi, 15)
     assert rel(gw, ow) <= TOL64
 
