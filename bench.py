@@ -54,6 +54,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
 
@@ -80,6 +81,47 @@ def time_solver(W, prec, steps, warmup):
     ms = e0.elapsed_time(e1)
     s.close()
     return ms, dt, kb, tiling
+
+
+def time_adjoint(steps=None):
+    """Adjoint workload (a = 0.6, m = 2, 4096 x 256, 20000 steps, source r0 = 10,
+    observer r* = 300): wall time of the forward run with the waveform
+    recorded, and of the reverse sweep that returns dL/dPhi0, dL/dPi0,
+    dL/dr0 and dL/damp for L = sum |w|^2 (no forward state kept)."""
+    import torch
+    from paper_0909_4039_amd import inputs, workloads
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    W = workloads.ADJOINT
+    n = steps or W.steps
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+    s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt)
+    s.set_source(W.r0, W.amp)
+    phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
+                           inputs.seeded_amplitude(W.pulse["seed"]))
+
+    def forward():
+        s.set_state(phi, pi)
+        s.set_time(0.0, 0)
+        s.set_observer(W.rstar_obs, n + 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.step(n)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    forward()                       # warm-up
+    fwd = min(forward() for _ in range(3))
+    g = (2.0 * s.wave).contiguous()
+    s.adjoint(g, n, W.rstar_obs)    # warm-up
+    adj = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.adjoint(g, n, W.rstar_obs)
+        adj.append(time.perf_counter() - t)
+    s.close()
+    return {"workload": W.name, "steps": n, "forward_ms": fwd * 1e3, "adjoint_ms": min(adj) * 1e3,
+            "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0}
 
 
 def cpu_baseline(W, seconds):
@@ -156,6 +198,8 @@ def main():
                        "hbm_frac_per_launch": BYTES_PER_UPDATE[32] * pts / l32 / HBM_PEAK,
                        "effective_frac": BYTES_PER_UPDATE[32] * ups32 / HBM_PEAK,
                        "traffic": measured_traffic(32)}
+    if not args.no_adjoint:
+        out["adjoint"] = time_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -125,6 +125,34 @@ int teuk_get_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* order);
 int teuk_set_blocking(teuk_ctx* ctx, int32_t steps_per_launch);
 int teuk_get_blocking(teuk_ctx* ctx);
 
+/* Reverse sweep (FP64 contexts only).  The time step of Eqs. (13)-(14) is
+ * affine in u = (Phi, Pi), u^{k+1} = K u^k + s^k, with K independent of u
+ * and k; s^k carries the source T at t^k and t^k + dt/2.  For a real loss
+ * L of the waveform w^k = E u^k (k = 0..n_steps) recorded at rstar_obs
+ * (linear interpolation in r*, as teuk_set_observer) from initial data
+ * u^0 at time t_start, this returns the gradients of L with respect to the
+ * initial data and the source parameters of teuk_set_source:
+ *   lambda^n = E^H g^n,  lambda^k = K^H lambda^{k+1} + E^H g^k,
+ *   dL/du^0 = lambda^0,  dL/dp = sum_k Re <a_T^k, dT^k/dp>,
+ * with a_T^k the adjoints of the source values of step k.  K^H needs no
+ * forward state, so no forward steps are stored or recomputed.
+ *
+ * Complex gradients use the real-view convention g = dL/dRe + i dL/dIm
+ * (the convention of torch's complex autograd: for L = |z|^2, g = 2z).
+ *   dL_dwave: device, (n_steps + 1) x n_theta complex128, row k = g^k (read).
+ *   workspace: device, >= teuk_adjoint_workspace_bytes bytes, 256-byte
+ *     aligned, caller-owned; contents are scratch.
+ *   dL_dphi0, dL_dpi0: device, n_theta x n_rstar complex128 (written).
+ *   dL_dr0, dL_damp: host, may be NULL; both 0 if no source was set.
+ * Uses the context's dt, source, tiling and steps per launch, and neither
+ * reads nor changes the bound state or the time.  Synchronous (returns
+ * after the sweep).  TEUK_ENOTSUP for FP32 contexts; TEUK_EINVAL for
+ * misaligned, overlapping or short buffers or rstar_obs outside the grid. */
+int64_t teuk_adjoint_workspace_bytes(teuk_ctx* ctx);
+int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+                 void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
+                 double* dL_damp);
+
 /* Scan the current state for non-finite values (synchronous).  Returns
  * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */
 int teuk_check_finite(teuk_ctx* ctx);

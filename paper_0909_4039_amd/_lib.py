@@ -43,6 +43,9 @@ _SIGS = {
     "teuk_get_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_set_blocking": (ctypes.c_int, [_P, _I32]),
     "teuk_get_blocking": (ctypes.c_int, [_P]),
+    "teuk_adjoint_workspace_bytes": (_I64, [_P]),
+    "teuk_adjoint": (ctypes.c_int, [_P, _D, _P, _I64, _D, _P, _I64, _P, _P, ctypes.POINTER(_D),
+                                    ctypes.POINTER(_D)]),
     "teuk_check_finite": (ctypes.c_int, [_P]),
     "teuk_status": (ctypes.c_int, [_P]),
     "teuk_last_error": (ctypes.c_char_p, [_P]),

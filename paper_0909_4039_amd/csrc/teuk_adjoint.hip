@@ -1,0 +1,401 @@
+// HIP kernels of libteuk for gfx950 (MI355X): the reverse (adjoint) sweep.
+//
+// One Lax-Wendroff step (paper Eqs. 13-14) is affine in u = (Phi, Pi):
+// u^{n+1} = K u^n + s^n, where K does not depend on u or n and s^n carries
+// the particle source T at t^n (predictor) and t^n + dt/2 (corrector).  For
+// a real loss L(w^0..w^N) of the recorded waveform w^k = E u^k, the
+// adjoint lambda^k = dL/du^k obeys
+//   lambda^N = E^H g^N,   lambda^k = K^H lambda^{k+1} + E^H g^k,
+// with g^k = dL/dRe w^k + i dL/dIm w^k, and the source parameters get
+//   dL/dp = sum_k Re sum_points conj(a_T) dT/dp,
+// where a_T is the adjoint of the source value at each point and stage.
+// K^H needs no forward state, so the sweep runs backwards from the loss
+// alone: no stored or recomputed forward steps.
+//
+// adj_step_kernel applies KB reverse steps per launch with the same tiling
+// as the forward kernel: a wavefront owns a strip of 64 r* columns and
+// marches up through a chunk of theta rows.  The reverse step has the
+// forward step's footprint (r* +-1, theta +-2), with the lane shifts
+// mirrored: the reverse corrector sends a half point's adjoint from column
+// c+1 down to c, the reverse predictor from c-1 up to c.  The transposed
+// angular stencil sum_j' w(j', j) z(j') is accumulated as a partial sum,
+// like the forward stencil.  Traffic: one read of lambda^{n+KB} and one
+// write of lambda^n, 64 B per grid point per launch, plus the g rows.
+//
+// Source gradients: each wave accumulates, over the points it owns (its
+// output columns and its chunk's rows), Re c, Re c * x and t Im c with
+// c = conj(a_T) e^{-i m Omega t} G, G the source Gaussian and x = d ln G /
+// d r*0; rows where the theta Gaussian is exactly zero add nothing and are
+// skipped.  The per-wave sums are added into a fixed slot per (block,
+// wave), so the result does not depend on scheduling, and one block sums
+// the slots in a fixed order at the end.
+#include "teuk_device.h"
+
+namespace teuk {
+
+using C = cx<double>;
+
+// Reverse of the non-angular part of one stage of length tau at one point.
+// The forward stage maps means (f, g) and r* differences (df, dg) of
+// (Phi, Pi) to
+//   Phi' = f0 + tau (g - b df)
+//   Pi'  = g0 + tau (b dg + T - y^2 [CR df + V f + CT (g - b df)]) + tau Delta y^2 Lth f
+// (the forward kernel's stage()).  Given adjoints (yP, yQ) of (Phi', Pi')
+// and W = tau y^2 yQ:
+//   a_g  = tau yP - conj(CT) W
+//   a_df = -b a_g - conj(CR) W
+//   a_f  = -conj(V) W           (+ Lth^T (Delta W), formed across rows)
+//   a_dg = tau b yQ
+//   z    = Delta W              (what the transposed angular stencil acts on)
+// The direct terms (f0, g0) are added by the caller.
+struct AStage {
+    C ag, adf, af, adg, z;
+};
+
+__device__ __forceinline__ AStage astage(const Rad<double>& q, const Ang<double>& g, double m2ma, double tau,
+                                         C yP, C yQ) {
+    double S2 = fma(q.w2, q.w2, -g.a2s2 * q.del);   // Sigma^2
+    double y = rsqrt_full(S2);
+    double y2 = y * y;
+    double b = q.w2 * y;
+    C CR = {fma(q.wbn * g.sin2, y2, q.crr), m2ma * q.w2};
+    C CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
+    C V = {q.vr, q.vi};
+    C W = (tau * y2) * yQ;
+    AStage o;
+    C t = cmulc(CT, W);
+    o.ag = {fma(tau, yP.re, -t.re), fma(tau, yP.im, -t.im)};
+    C u = cmulc(CR, W);
+    o.adf = {fma(-b, o.ag.re, -u.re), fma(-b, o.ag.im, -u.im)};
+    C v = cmulc(V, W);
+    o.af = {-v.re, -v.im};
+    o.adg = (tau * b) * yQ;
+    o.z = q.del * W;
+    return o;
+}
+
+// Unit-amplitude theta Gaussian of the source at a row (wave-uniform).
+__device__ __forceinline__ double load_gth(const double* __restrict__ ang, int row) {
+    return ang[(int64_t)row * A_STRIDE + A_GTH];
+}
+
+// Source-gradient sums of one wave (see the file comment).
+struct GradAcc {
+    double sa, sx, st;
+};
+
+// a_T = tau yQ at a point with source Gaussian G = gth * gr, log-derivative
+// x, phase ph and time t.
+__device__ __forceinline__ void grad_add(GradAcc& acc, double tau, C yQ, double gth, double gr, double x, C ph,
+                                         double t) {
+    C c = (tau * gth * gr) * cmulc(yQ, ph);
+    acc.sa += c.re;
+    acc.sx = fma(c.re, x, acc.sx);
+    acc.st = fma(t, c.im, acc.st);
+}
+
+// State of one reverse step marching upwards through theta.  At iteration
+// L (input row L of lambda^{n+1}) the stage
+//   A: runs the reverse corrector at integer row L,
+//   B: finishes row L-1's reverse corrector, forms the half-point adjoints
+//      of half row L-1 and runs the reverse predictor there; emits the Pi
+//      adjoint of output row L-1,
+//   C: finishes half row L-2's reverse predictor and emits the Phi adjoint
+//      of output row L-2.
+struct APipe {
+    C tz;        // wp_{L-1} z_{L-1}: the transposed corrector stencil's carry
+    C apc;       // corrector a_f of row L-1 without wm_L z_L
+    C adp;       // corrector a_df of row L-1
+    C ahq;       // Pi adjoint of half row L-1 (complete)
+    C th;        // wp_{L-2} zh_{L-2}: the transposed predictor stencil's carry
+    C bpb;       // predictor a_f (with the direct term) of half row L-2 without wm_{L-1} zh_{L-1}
+    C bdp;       // predictor a_df of half row L-2
+    C yp1, yp2;  // kept Phi adjoint input of rows L-1, L-2 (direct term of the output)
+    C yq1;       // kept Pi adjoint input of row L-1
+    int olo, ohi;  // output rows [olo, ohi)
+    int ilo, ihi;  // input rows [ilo, ihi)
+    int hlo, hhi;  // half rows [hlo, hhi]
+};
+
+__device__ __forceinline__ void apipe_init(APipe& st, int olo, int ohi, int nth) {
+    const C z = {0.0, 0.0};
+    st.tz = z; st.apc = z; st.adp = z; st.ahq = z; st.th = z; st.bpb = z; st.bdp = z;
+    st.yp1 = z; st.yp2 = z; st.yq1 = z;
+    st.olo = olo; st.ohi = ohi;
+    st.ilo = max(olo - 2, 0);
+    st.ihi = min(ohi + 2, nth);
+    st.hlo = max(olo - 1, 0);
+    st.hhi = min(ohi, nth - 1);
+}
+
+struct AConsts {
+    const double* ang;
+    const double* xr_i;   // radial log-derivative of the source Gaussian, integer / half nodes
+    const double* xr_h;
+    const double (*srad)[N_RAD_USED][WAVE];
+    int lane, nth, c, iobs;
+    unsigned cu;
+    double keep, idr, dt, hdt, m2ma, alpha;
+    bool own_col;          // this lane's column is one of the wave's outputs
+    int own_lo, own_hi;    // rows whose source gradients this wave adds
+};
+
+// Per-stage (per reversed step) constants.
+struct AStep {
+    C ph0, ph1;            // e^{-i m Omega t}, e^{-i m Omega (t + dt/2)}
+    double t0, t1;
+    const double* grow;    // g row injected into this stage's output (NULL: none)
+};
+
+__device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AStep& S, int L, C p, C q,
+                                           GradAcc& acc, C& outP, bool& okP, C& outQ, bool& okQ) {
+    const double half = 0.5;
+    const C zero = {0.0, 0.0};
+    const int H = L - 1, R = L - 2;
+    // ---- A: reverse corrector at integer row L
+    C yP = zero, yQ = zero, apcH = st.apc, apcL = zero, adpL = zero, ahqL = zero, tz = zero;
+    if (L >= st.ilo && L < st.ihi) {
+        yP = K.keep * p;
+        yQ = K.keep * q;
+        const Ang<double> g = load_ang(K.ang, L);
+        const Rad<double> qi = lds_rad<double>(K.srad[1], K.lane);
+        AStage o = astage(qi, g, K.m2ma, K.dt, yP, yQ);
+        apcH = rfma(g.wm, o.z, st.apc);                       // row L-1 complete
+        apcL = rfma(g.w0, o.z, o.af + st.tz);
+        tz = g.wp * o.z;
+        adpL = o.adf;
+        // Pi adjoint of half point c+1/2: 0.5 (aQc_c + aQc_{c+1}) + (adQ_c - adQ_{c+1}) / dr
+        C lo = rfma(K.idr, o.adg, half * o.ag);
+        C hi = rfma(-K.idr, o.adg, half * o.ag);
+        ahqL = lo + shfl_dn1(hi);
+        const double gth = load_gth(K.ang, L);
+        if (K.own_col && L >= K.own_lo && L < K.own_hi && gth != 0.0)
+            grad_add(acc, K.dt, yQ, gth, qi.gr, K.xr_i[K.cu], S.ph1, S.t1);
+    }
+    // ---- B: reverse predictor at half row H
+    C bpbR = st.bpb, bpbH = zero, bdpH = zero, th = zero;
+    okQ = false;
+    if (H >= st.hlo && H <= st.hhi) {
+        C ahp = rfma(K.idr, st.adp, half * apcH) + shfl_dn1(rfma(-K.idr, st.adp, half * apcH));
+        C ahq = st.ahq;
+        const Ang<double> g = load_ang(K.ang, H);
+        const Rad<double> qh = lds_rad<double>(K.srad[0], K.lane);
+        AStage o = astage(qh, g, K.m2ma, K.hdt, ahp, ahq);
+        C bqb = ahq + o.ag;
+        bpbR = rfma(g.wm, o.z, st.bpb);                       // half row H-1 complete
+        bpbH = rfma(g.w0, o.z, (ahp + o.af) + st.th);
+        th = g.wp * o.z;
+        bdpH = o.adf;
+        okQ = (H >= st.olo && H < st.ohi);
+        if (okQ) {
+            // Pi adjoint of output column c: 0.5 (bQb_c + bQb_{c-1}) + (bdQ_{c-1} - bdQ_c) / dr
+            C lo = rfma(-K.idr, o.adg, half * bqb);
+            C hi = rfma(K.idr, o.adg, half * bqb);
+            outQ = st.yq1 + lo + shfl_up1(hi);
+        }
+        const double gth = load_gth(K.ang, H);
+        if (K.own_col && H >= K.own_lo && H < K.own_hi && gth != 0.0)
+            grad_add(acc, K.hdt, ahq, gth, qh.gr, K.xr_h[K.cu], S.ph0, S.t0);
+    }
+    // ---- C: Phi adjoint of output row R
+    okP = (R >= st.olo && R < st.ohi);
+    if (okP) {
+        C lo = rfma(-K.idr, st.bdp, half * bpbR);
+        C hi = rfma(K.idr, st.bdp, half * bpbR);
+        C v = st.yp2 + lo + shfl_up1(hi);
+        if (S.grow != nullptr && (K.c == K.iobs || K.c == K.iobs + 1)) {
+            C gv = ldc(S.grow, R);
+            v = rfma(K.c == K.iobs ? 1.0 - K.alpha : K.alpha, gv, v);
+        }
+        outP = v;
+    }
+    // ---- carries
+    st.tz = tz;
+    st.apc = apcL;
+    st.adp = adpL;
+    st.ahq = ahqL;
+    st.th = th;
+    st.bpb = bpbH;
+    st.bdp = bdpH;
+    st.yp2 = st.yp1;
+    st.yp1 = yP;
+    st.yq1 = yQ;
+}
+
+template <int KB>
+__global__ __launch_bounds__(256) void adj_step_kernel(const double* __restrict__ lp, const double* __restrict__ lq,
+                                                     double* __restrict__ lp_out, double* __restrict__ lq_out,
+                                                     const double* __restrict__ rad_i,
+                                                     const double* __restrict__ rad_h,
+                                                     const double* __restrict__ ang, AdjArgs A) {
+    constexpr int SO = WAVE - 2 * KB;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = blk / ngrp;
+    const int grp = blk - chunk * ngrp;
+    const int strip = grp * WG_WAVES + wid;
+    if (strip >= A.n_strips) return;   // wave-uniform; the kernel has no barriers
+    const int nr = A.nr, nth = A.nth;
+    const int c = strip * SO - KB + lane;
+    const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
+    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    double (*srad)[N_RAD_USED][WAVE] = srad_all[wid];
+    for (int k = 0; k < 2 * N_RAD_USED; ++k) {
+        const int loc = k / N_RAD_USED, f = k % N_RAD_USED;
+        srad[loc][f][lane] = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride + cu];
+    }
+    const int j0 = chunk * A.rows;
+    const int jend = min(j0 + A.rows, nth);
+    const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
+    const unsigned boff = cu * (unsigned)(2 * sizeof(double));
+    const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(double));
+    AConsts K;
+    K.ang = ang;
+    K.xr_i = rad_i + (int64_t)R_XR * A.stride;
+    K.xr_h = rad_h + (int64_t)R_XR * A.stride;
+    K.srad = srad;
+    K.lane = lane;
+    K.nth = nth;
+    K.c = c;
+    K.cu = cu;
+    K.iobs = A.iobs;
+    K.alpha = A.alpha;
+    // boundary columns (Dirichlet) and lanes outside the grid carry no adjoint
+    K.keep = (c <= 0 || c >= nr - 1) ? 0.0 : 1.0;
+    K.idr = A.inv_dr;
+    K.dt = A.dt;
+    K.hdt = A.hdt;
+    K.m2ma = A.m2ma;
+    K.own_col = out_lane;
+    K.own_lo = j0;
+    K.own_hi = jend;
+
+    AStep S[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        S[k].ph0 = {A.ph[2 * k][0], A.ph[2 * k][1]};
+        S[k].ph1 = {A.ph[2 * k + 1][0], A.ph[2 * k + 1][1]};
+        S[k].t0 = A.t[2 * k];
+        S[k].t1 = A.t[2 * k + 1];
+        S[k].grow = A.g_row[k] >= 0 ? A.g + 2 * A.g_row[k] * (int64_t)nth : nullptr;
+    }
+    APipe st[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        apipe_init(st[k], max(j0 - 2 * (KB - 1 - k), 0), min(jend + 2 * (KB - 1 - k), nth), nth);
+    const int Ls = max(st[0].olo - 2, 0);
+    const int Le = jend - 1 + 2 * KB;
+    const C zero = {0.0, 0.0};
+    C heldQ[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) heldQ[k] = zero;
+    GradAcc acc = {0.0, 0.0, 0.0};
+
+    C pf_p = ld_row_once(lp, (int64_t)Ls * nr, boff), pf_q = ld_row_once(lq, (int64_t)Ls * nr, boff);
+
+    auto iter = [&](int L) {
+        if (L > Le) return;
+        C p = pf_p, q = pf_q;
+        if (L + 1 < st[0].ihi && L + 1 <= Le) {
+            const int64_t row = (int64_t)(L + 1) * nr;
+            pf_p = ld_row_once(lp, row, boff);
+            pf_q = ld_row_once(lq, row, boff);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int Lk = L - 2 * k;
+            C oP = zero, oQ = zero;
+            bool okP, okQ;
+            apipe_iter(st[k], K, S[k], Lk, p, q, acc, oP, okP, oQ, okQ);
+            if (k == KB - 1) {
+                if (okQ && out_lane) st_row(lq_out, (int64_t)(Lk - 1) * nr, soff, oQ);
+                if (okP && out_lane) st_row(lp_out, (int64_t)(Lk - 2) * nr, soff, oP);
+            } else {
+                // next stage's input row Lk-2: Pi finished one iteration ago,
+                // Phi finished now
+                p = oP;
+                q = heldQ[k];
+                if (okQ) heldQ[k] = oQ;
+            }
+        }
+    };
+    for (int L = Ls; L <= Le; L += 2) {
+        iter(L);
+        iter(L + 1);
+    }
+    // wave sums in a fixed butterfly order, added into this wave's slot
+    double v[3] = {acc.sa, acc.sx, acc.st};
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, WAVE);
+    if (lane == 0) {
+        double* slot = A.slots + ((int64_t)blockIdx.x * WG_WAVES + wid) * 3;
+        slot[0] += v[0];
+        slot[1] += v[1];
+        slot[2] += v[2];
+    }
+}
+
+void launch_adjoint_step(const AdjArgs& a, hipStream_t s) {
+    int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
+    if (a.kb == 2)
+        hipLaunchKernelGGL(adj_step_kernel<2>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
+                           a.lq_out, a.rad_i, a.rad_h, a.ang, a);
+    else
+        hipLaunchKernelGGL(adj_step_kernel<1>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
+                           a.lq_out, a.rad_i, a.rad_h, a.ang, a);
+}
+
+// lambda^N = E^H g^N on a zeroed state: (1 - alpha) g_j at column iobs and
+// alpha g_j at iobs + 1 of the Phi adjoint; the Pi adjoint is zero.
+__global__ void adj_init_kernel(double* __restrict__ lp, double* __restrict__ lq, const double* __restrict__ g,
+                                int64_t n, int nr, int iobs, double alpha) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (; k < n; k += step) {
+        const int64_t j = k / nr;
+        const int i = (int)(k - j * nr);
+        C v = {0.0, 0.0};
+        if (g != nullptr && (i == iobs || i == iobs + 1)) v = (i == iobs ? 1.0 - alpha : alpha) * ldc(g, j);
+        stc(lp, k, v);
+        stc(lq, k, C{0.0, 0.0});
+    }
+}
+void launch_adjoint_init(double* lp, double* lq, const double* g_row, int64_t n, int nr, int iobs, double alpha,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(adj_init_kernel, dim3(2048), dim3(256), 0, s, lp, lq, g_row, n, nr, iobs, alpha);
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ x, int64_t n) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[k] = 0.0;
+}
+void launch_fill_zero(double* x, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+}
+
+// Sum the per-wave slots ([n_slots][3]) in a fixed order into out[3].
+__global__ __launch_bounds__(256) void slot_sum_kernel(const double* __restrict__ slots, int64_t n_slots,
+                                                        double* __restrict__ out) {
+    __shared__ double part[3][256];
+    const int t = threadIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = t; i < n_slots; i += 256)
+        for (int q = 0; q < 3; ++q) s[q] += slots[i * 3 + q];
+    for (int q = 0; q < 3; ++q) part[q][t] = s[q];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < 3; ++q) part[q][t] += part[q][t + w];
+        __syncthreads();
+    }
+    if (t < 3) out[t] = part[t][0];
+}
+void launch_slot_sum(const double* slots, int64_t n_slots, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(slot_sum_kernel, dim3(1), dim3(256), 0, s, slots, n_slots, out);
+}
+
+}  // namespace teuk

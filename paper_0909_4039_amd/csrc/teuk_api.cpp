@@ -178,6 +178,109 @@ int launch_steps(teuk_ctx* c, int64_t n) {
     return TEUK_OK;
 }
 
+// Blocks of the reverse sweep's launch grid: the larger of the one- and
+// two-step grids at the current tiling.
+int64_t adjoint_blocks(const teuk_ctx* c) {
+    const Geometry& g = c->geo;
+    const int64_t nchunks = (g.nth + c->rows - 1) / c->rows;
+    int64_t best = 0;
+    for (int kb = 1; kb <= KB_MAX; ++kb) {
+        const int64_t so = WAVE - 2 * kb;
+        const int64_t strips = (g.nr + so - 1) / so;
+        best = std::max(best, (strips + WG_WAVES - 1) / WG_WAVES * nchunks);
+    }
+    return best;
+}
+
+int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// Workspace layout: [lambda Phi][lambda Pi] (complex128 [nth][nr] each),
+// then the per-wave gradient slots, then 4 doubles of result.
+struct AdjLayout {
+    int64_t lam, slots, result, total, n_slots;
+};
+AdjLayout adjoint_layout(const teuk_ctx* c) {
+    AdjLayout L;
+    const int64_t n = c->geo.nr * c->geo.nth;
+    L.n_slots = adjoint_blocks(c) * WG_WAVES;
+    L.lam = 0;
+    L.slots = round256(2 * n * 16);
+    L.result = L.slots + round256(L.n_slots * 3 * 8);
+    L.total = L.result + 256;
+    return L;
+}
+
+int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t n, double t_start, char* ws,
+                  double* dphi0, double* dpi0, double* res_host) {
+    const Geometry& geo = c->geo;
+    const AdjLayout lay = adjoint_layout(c);
+    const int64_t npts = geo.nr * geo.nth;
+    double* wl[2] = {(double*)(ws + lay.lam), (double*)(ws + lay.lam) + 2 * npts};
+    double* slots = (double*)(ws + lay.slots);
+    double* result = (double*)(ws + lay.result);
+    // launches from the top: kb steps each, the odd remainder last
+    std::vector<int> plan;
+    for (int64_t r = n; r > 0;) {
+        const int kb = (c->kblock >= 2 && r >= 2) ? 2 : 1;
+        plan.push_back(kb);
+        r -= kb;
+    }
+    // start in the pair that makes the last launch write (dphi0, dpi0)
+    double* pair[2][2] = {{dphi0, dpi0}, {wl[0], wl[1]}};
+    int cur = (plan.size() % 2 == 1) ? 1 : 0;
+    launch_adjoint_init(pair[cur][0], pair[cur][1], g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    launch_fill_zero(slots, lay.n_slots * 3, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    AdjArgs a{};
+    a.rad_i = (const double*)c->d_rad_i;
+    a.rad_h = (const double*)c->d_rad_h;
+    a.ang = (const double*)c->d_ang;
+    a.stride = geo.stride;
+    a.nr = (int)geo.nr;
+    a.nth = (int)geo.nth;
+    a.rows = c->rows;
+    a.n_chunks = (int)((geo.nth + c->rows - 1) / c->rows);
+    a.dt = c->dt;
+    a.hdt = 0.5 * c->dt;
+    a.inv_dr = 1.0 / geo.dr;
+    a.m2ma = -2.0 * geo.m * geo.a;
+    a.g = g;
+    a.iobs = iobs;
+    a.alpha = alpha;
+    a.slots = slots;
+    int64_t top = n;   // this launch reads lambda^top
+    for (int kb : plan) {
+        a.kb = kb;
+        a.n_strips = (int)((geo.nr + (WAVE - 2 * kb) - 1) / (WAVE - 2 * kb));
+        for (int k = 0; k < KB_MAX; ++k) {
+            const int64_t step = top - 1 - k;   // forward step reversed by stage k
+            const double t0 = t_start + double(step) * c->dt, t1 = t0 + 0.5 * c->dt;
+            const double w0 = geo.m * c->Omega * t0, w1 = geo.m * c->Omega * t1;
+            a.t[2 * k] = t0;
+            a.t[2 * k + 1] = t1;
+            a.ph[2 * k][0] = std::cos(w0);
+            a.ph[2 * k][1] = -std::sin(w0);
+            a.ph[2 * k + 1][0] = std::cos(w1);
+            a.ph[2 * k + 1][1] = -std::sin(w1);
+            a.g_row[k] = (k < kb) ? step : -1;
+        }
+        a.lp = pair[cur][0];
+        a.lq = pair[cur][1];
+        a.lp_out = pair[1 - cur][0];
+        a.lq_out = pair[1 - cur][1];
+        launch_adjoint_step(a, c->stream);
+        HIP_TRY(c, hipGetLastError());
+        cur = 1 - cur;
+        top -= kb;
+    }
+    launch_slot_sum(slots, lay.n_slots, result, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(res_host, result, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TEUK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -369,6 +472,62 @@ int teuk_get_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* order) {
     if (!c) return TEUK_EINVAL;
     if (rows_per_wave) *rows_per_wave = c->rows;
     if (order) *order = c->order;
+    return TEUK_OK;
+}
+
+int64_t teuk_adjoint_workspace_bytes(teuk_ctx* c) {
+    if (!c) return TEUK_EINVAL;
+    if (c->prec != TEUK_FP64) return TEUK_ENOTSUP;
+    return adjoint_layout(c).total;
+}
+
+int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+                 void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
+                 double* dL_damp) {
+    if (!c) return TEUK_EINVAL;
+    if (c->status != TEUK_OK) return c->status;
+    if (c->prec != TEUK_FP64) return fail(c, TEUK_ENOTSUP, "the reverse sweep is FP64 only");
+    if (n_steps < 0) return fail(c, TEUK_EINVAL, "negative step count");
+    if (!std::isfinite(t_start)) return fail(c, TEUK_EINVAL, "non-finite t_start");
+    if (!dL_dwave || !workspace || !dL_dphi0 || !dL_dpi0) return fail(c, TEUK_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % 256 != 0) return fail(c, TEUK_EINVAL, "workspace not 256-byte aligned");
+    if ((uintptr_t)dL_dwave % 16 != 0 || (uintptr_t)dL_dphi0 % 16 != 0 || (uintptr_t)dL_dpi0 % 16 != 0)
+        return fail(c, TEUK_EINVAL, "dL_dwave, dL_dphi0 and dL_dpi0 must be 16-byte aligned");
+    if (dL_dphi0 == dL_dpi0) return fail(c, TEUK_EINVAL, "dL_dphi0 and dL_dpi0 alias");
+    const AdjLayout lay = adjoint_layout(c);
+    if (workspace_bytes < lay.total)
+        return fail(c, TEUK_EINVAL, "workspace of %lld B is smaller than the %lld B needed", (long long)workspace_bytes,
+                    (long long)lay.total);
+    const Geometry& g = c->geo;
+    const int64_t nb = 2 * g.nr * g.nth * 16;
+    auto overlap = [](const void* a, int64_t na, const void* b, int64_t nbb) {
+        return (const char*)a < (const char*)b + nbb && (const char*)b < (const char*)a + na;
+    };
+    if (overlap(workspace, lay.total, dL_dphi0, nb / 2) || overlap(workspace, lay.total, dL_dpi0, nb / 2) ||
+        overlap(dL_dphi0, nb / 2, dL_dpi0, nb / 2))
+        return fail(c, TEUK_EINVAL, "workspace and output buffers overlap");
+    int iobs;
+    double alpha;
+    if (!observer_index(g, rstar_obs, iobs, alpha))
+        return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
+    double res[3] = {0.0, 0.0, 0.0};
+    int rc = adjoint_sweep(c, iobs, alpha, (const double*)dL_dwave, n_steps, t_start, (char*)workspace,
+                           (double*)dL_dphi0, (double*)dL_dpi0, res);
+    if (rc != TEUK_OK) return rc;
+    // dT/damp = G e^{-i m Omega t};
+    // dT/dr0 = amp G e^{-i m Omega t} [x dr*0/dr0 - i m t dOmega/dr0],
+    // x = (r* - r*0)/sr^2, dr*/dr = (r^2 + a^2)/Delta (Eq. 2).
+    double damp = 0.0, dr0 = 0.0;
+    if (c->has_src) {
+        const double r0 = c->r0, a = g.a, M = g.M;
+        const double drs0 = (r0 * r0 + a * a) / (r0 * r0 - 2.0 * M * r0 + a * a);
+        const double den = std::pow(r0, 1.5) + a * std::sqrt(M);
+        const double dOm = -1.5 * std::sqrt(M) * std::sqrt(r0) / (den * den);
+        damp = res[0];
+        dr0 = c->amp * (drs0 * res[1] + double(g.m) * dOm * res[2]);
+    }
+    if (dL_damp) *dL_damp = damp;
+    if (dL_dr0) *dL_dr0 = dr0;
     return TEUK_OK;
 }
 

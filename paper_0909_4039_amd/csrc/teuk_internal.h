@@ -100,6 +100,31 @@ struct StepArgs {
     R alpha;
 };
 
+// Arguments of one launch of the reverse sweep (FP64 only).  Stage k of a
+// launch reverses forward step g_row[k]: it reads lambda^{g_row[k]+1} and
+// writes lambda^{g_row[k]}; t[2k], t[2k+1] and ph[2k], ph[2k+1] are that
+// step's predictor and corrector times and source phases.
+struct AdjArgs {
+    const double* lp;     // lambda^{n+kb}: interleaved complex [nth][nr]
+    const double* lq;
+    double* lp_out;       // lambda^n
+    double* lq_out;
+    const double* rad_i;
+    const double* rad_h;
+    const double* ang;
+    int64_t stride;
+    int32_t nr, nth;
+    int32_t rows, n_strips, n_chunks, kb;
+    double dt, hdt, inv_dr, m2ma;
+    double ph[2 * KB_MAX][2];
+    double t[2 * KB_MAX];
+    const double* g;      // dL/dw rows [n + 1][nth]
+    int64_t g_row[KB_MAX];
+    int32_t iobs;
+    double alpha;
+    double* slots;        // [blocks][WG_WAVES][3] source-gradient partial sums
+};
+
 constexpr int WAVE = 64;
 constexpr int WG_WAVES = 4;
 
@@ -109,6 +134,11 @@ void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int io
                          hipStream_t s);
 void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs, float alpha,
                          hipStream_t s);
+void launch_adjoint_step(const AdjArgs& a, hipStream_t s);
+void launch_adjoint_init(double* lp, double* lq, const double* g_row, int64_t n, int nr, int iobs, double alpha,
+                         hipStream_t s);
+void launch_fill_zero(double* x, int64_t n, hipStream_t s);
+void launch_slot_sum(const double* slots, int64_t n_slots, double* out, hipStream_t s);
 void launch_count_nonfinite_fp64(const double* x, int64_t n, unsigned int* flag, hipStream_t s);
 void launch_count_nonfinite_fp32(const float* x, int64_t n, unsigned int* flag, hipStream_t s);
 

@@ -55,6 +55,7 @@ class Solver:
             self._ctx = ctx
             check(_lib.lib().teuk_bind_state(self._ctx, *[b.data_ptr() for b in self._bufs]), self._ctx)
         self.wave = None
+        self.source = None
 
     # ------------------------------------------------------------ state
     def _cur(self):
@@ -77,6 +78,7 @@ class Solver:
     # ------------------------------------------------------------ physics
     def set_source(self, r0, amp, sigma_r_cells=2.0, sigma_th_cells=2.0):
         check(_lib.lib().teuk_set_source(self._ctx, r0, amp, sigma_r_cells, sigma_th_cells), self._ctx)
+        self.source = (float(r0), float(amp), float(sigma_r_cells), float(sigma_th_cells))
 
     def set_observer(self, rstar_obs, capacity_rows):
         """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
@@ -121,6 +123,35 @@ class Solver:
         o = ctypes.c_int32()
         check(_lib.lib().teuk_get_tiling(self._ctx, ctypes.byref(r), ctypes.byref(o)), self._ctx)
         return r.value, o.value
+
+    def adjoint(self, dL_dwave, n_steps, rstar_obs, t_start=0.0):
+        """Reverse sweep of the library (FP64): gradients of a real loss of the
+        waveform w^0..w^n recorded at rstar_obs from initial data at t_start.
+
+        ``dL_dwave`` is (n_steps + 1, n_theta) complex, dL/dRe w + i dL/dIm w.
+        Returns (dL/dPhi0, dL/dPi0, dL/dr0, dL/damp) in the same convention;
+        the source is the one last given to ``set_source``.
+        """
+        n = int(n_steps)
+        g = torch.as_tensor(dL_dwave).to(self.device, torch.complex128).contiguous()
+        if g.shape != (n + 1, self.shape[0]):
+            raise ValueError(f"dL_dwave has shape {tuple(g.shape)}, expected {(n + 1, self.shape[0])}")
+        nbytes = check_int(_lib.lib().teuk_adjoint_workspace_bytes(self._ctx))
+        ws = torch.empty((nbytes + 255) // 8 + 32, dtype=torch.float64, device=self.device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        dphi = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        dpi = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        dr0 = ctypes.c_double()
+        damp = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            # the library works on its own stream; order it after the producers of g
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            check(_lib.lib().teuk_adjoint(self._ctx, float(rstar_obs), g.data_ptr(), n, float(t_start),
+                                          ctypes.c_void_p(base + off), int(ws.numel() * 8 - off),
+                                          dphi.data_ptr(), dpi.data_ptr(), ctypes.byref(dr0), ctypes.byref(damp)),
+                  self._ctx)
+        return dphi, dpi, dr0.value, damp.value
 
     def check_finite(self):
         """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""
