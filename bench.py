@@ -55,6 +55,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
 
@@ -65,6 +66,7 @@ def time_solver(W, prec, steps, warmup):
     dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
     s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
     s.set_source(W.r0, W.amp)
+    s.autotune(10)
     kb = s.get_blocking()
     tiling = s.get_tiling()
     s.set_observer(W.rstar_obs, warmup + steps + 1)
@@ -99,6 +101,9 @@ def time_adjoint(steps=None):
     phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
                            inputs.seeded_amplitude(W.pulse["seed"]))
 
+    s.set_state(phi, pi)
+    tuned = s.autotune(10)
+
     def forward():
         s.set_state(phi, pi)
         s.set_time(0.0, 0)
@@ -121,7 +126,72 @@ def time_adjoint(steps=None):
         adj.append(time.perf_counter() - t)
     s.close()
     return {"workload": W.name, "steps": n, "forward_ms": fwd * 1e3, "adjoint_ms": min(adj) * 1e3,
-            "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0}
+            "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0,
+            "rows_per_wave": tuned[0], "steps_per_launch": tuned[1]}
+
+
+def _pulse(w):
+    from paper_0909_4039_amd import inputs
+    p = w.pulse
+    return inputs.pulse(w.nr, w.nth, w.rstar_min, w.rstar_max, w.m, p["center"], p["width"], p["amplitude"])
+
+
+def time_batched(steps=200, graph_steps=20):
+    """The 32-instance batch (m = 1..8 x a in {0, 0.3, 0.6, 0.9}, uneven grids
+    from seed 3, pulses and sources, FP64, waveforms recorded): updates/s of
+    32 single-mode solvers stepped one after another (each autotuned) against
+    one batch (autotuned, one persistent launch per two steps, replayed from
+    a captured graph).  Results are bitwise identical between the two."""
+    import torch
+    from paper_0909_4039_amd import workloads
+    from paper_0909_4039_amd.batch import Batch, make_desc
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    ws = workloads.batched_instances()
+    pts = sum(w.nr * w.nth for w in ws)
+    dts = [suggest_dt(w.nr, w.nth, w.rstar_min, w.rstar_max, w.a, w.M, w.m, w.s, w.steps) for w in ws]
+    # per mode
+    solvers = []
+    for w, dt in zip(ws, dts):
+        s = Solver(w.nr, w.nth, w.rstar_min, w.rstar_max, w.a, w.M, w.m, w.s, dt)
+        s.set_source(w.r0, w.amp)
+        s.set_state(*_pulse(w))
+        s.set_observer(w.rstar_obs, 2 * steps + 1)
+        s.autotune(5)
+        solvers.append(s)
+    for s in solvers:
+        s.step(steps // 10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    per_mode = time.perf_counter() - t
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+    # batched
+    descs = [make_desc(w.nr, w.nth, w.rstar_min, w.rstar_max, w.a, w.m, dt, s=w.s, r0=w.r0, amp=w.amp,
+                       rstar_obs=w.rstar_obs) for w, dt in zip(ws, dts)]
+    b = Batch(descs, 2 * steps + 2 * graph_steps)
+    for i, w in enumerate(ws):
+        b.set_state(i, *_pulse(w))
+    rows, kb, persistent = b.autotune(5)
+    b.capture_graph(graph_steps)
+    b.step(graph_steps)
+    b.synchronize()
+    t = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    batched = time.perf_counter() - t
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": "batch_32_modes_seed3", "instances": len(ws), "points": pts, "steps": steps,
+            "per_mode_updates_per_s": pts * steps / per_mode, "batched_updates_per_s": pts * steps / batched,
+            "batched_over_per_mode": per_mode / batched, "batch_rows_per_wave": rows, "batch_steps_per_launch": kb,
+            "batch_persistent": persistent,
+            "graph_steps": graph_steps}
 
 
 def cpu_baseline(W, seconds):
@@ -200,6 +270,8 @@ def main():
                        "traffic": measured_traffic(32)}
     if not args.no_adjoint:
         out["adjoint"] = time_adjoint()
+    if not args.no_batched:
+        out["batched"] = time_batched()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

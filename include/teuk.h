@@ -153,6 +153,96 @@ int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t 
                  void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
                  double* dL_damp);
 
+/* Autotuner (synchronous): times launches_per_trial launches (after one
+ * warm-up launch) of every candidate tile shape -- theta rows per wavefront
+ * in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256} clipped to
+ * n_theta, times 1 or 2 steps per launch -- with HIP events on the
+ * context's stream, keeps the fastest (chunk-major order) and reports it in
+ * *rows_out and *kb_out (either may be NULL).  The results of teuk_step are
+ * bitwise identical for every candidate, so tuning changes speed only.
+ * Needs a bound state; the trial launches read the current pair and write
+ * the other one, so the state, time and waveform are unchanged.  The
+ * reverse sweep uses the same tiling. */
+int teuk_autotune(teuk_ctx* ctx, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out);
+
+/* ------------------------------------------------------------- batches
+ *
+ * After the ansatz of Eq. (4) every azimuthal mode m (and every spin a or s)
+ * is an independent 2+1 problem on its own grid (Sec. 2.2).  A batch steps
+ * many such instances, of different sizes, together: one persistent kernel
+ * launch advances every instance by 1 or 2 steps (the workgroups that fit
+ * on the GPU at once walk the batch's tile list), and teuk_batch_step can
+ * replay a captured HIP graph of such launches.  Per point the arithmetic
+ * is the single-mode step's, so each instance's states and waveform are
+ * bitwise identical to a teuk_ctx run with the same parameters started at
+ * t = 0, step 0.  FP64 only. */
+typedef struct {
+    teuk_grid grid;
+    double a, M;
+    int32_t m, s;
+    double dt;
+    double r0;              /* source orbit radius (> r+); 0: no source      */
+    double amp;             /* source amplitude (see teuk_set_source)        */
+    double sigma_r_cells;   /* source widths in cells; <= 0 selects 2        */
+    double sigma_th_cells;
+    double rstar_obs;       /* extraction radius, strictly inside the grid   */
+} teuk_desc;
+
+typedef struct teuk_batch teuk_batch;
+
+/* Create a batch of n instances (1..65535) described by descs, able to take
+ * up to max_steps steps in all (the source phase of every step is tabulated
+ * on the host at create, 32 B per step and instance).  The same checks as
+ * teuk_create apply to each descriptor.  hip_stream: hipStream_t for all
+ * work of the batch (graph capture needs a non-null stream).  The library
+ * allocates the instances' coefficient and phase tables. */
+int teuk_batch_create(int32_t n, const teuk_desc* descs, int64_t max_steps, void* hip_stream, teuk_batch** out);
+
+/* Release the batch (synchronises its stream first). */
+int teuk_batch_destroy(teuk_batch* b);
+
+/* Bind instance i's caller-owned device buffers: (phi, pi) hold its current
+ * state and (phi_next, pi_next) are the ping-pong partners, each
+ * n_theta x n_rstar complex128 (layout as teuk_bind_state); wave (may be
+ * NULL) receives its waveform rows [wave_rows][n_theta], row k = the state
+ * after k steps of the batch.  Every instance must be bound before the
+ * first step. */
+int teuk_batch_bind(teuk_batch* b, int32_t i, void* phi, void* pi, void* phi_next, void* pi_next, void* wave,
+                    int64_t wave_rows);
+
+/* Advance every instance n steps (Eqs. 13-14 with source and boundary
+ * conditions): replays of the captured graph while at least its step count
+ * remains, then direct launches.  TEUK_EINVAL past max_steps. */
+int teuk_batch_step(teuk_batch* b, int64_t n);
+
+/* Capture steps_per_graph steps (a positive multiple of the steps per
+ * launch) as a HIP graph that teuk_batch_step replays; 0 drops the graph.
+ * The kernels read the step and the current pair from a device-side
+ * clock, so every replay continues where the last one stopped.  Changing
+ * the tiling drops the graph. */
+int teuk_batch_capture_graph(teuk_batch* b, int64_t steps_per_graph);
+
+/* Tile shape for every instance (rows clipped to each n_theta; 0: the
+ * per-instance default), steps per launch (1 or 2) and launch form:
+ * persistent = 1 launches as many workgroups as stay resident, which walk
+ * the batch's tile list (each XCD a contiguous range); 0 launches one
+ * workgroup per tile.  Performance only; drops the graph. */
+int teuk_batch_set_tiling(teuk_batch* b, int32_t rows_per_wave, int32_t steps_per_launch, int32_t persistent);
+
+/* Autotuner: as teuk_autotune, over the whole batch (one rows value for all
+ * instances, clipped to each n_theta) and both launch forms; reports the
+ * choice (any out pointer may be NULL).  Trial launches leave the states,
+ * the step count and the waveforms unchanged.  Drops the graph. */
+int teuk_batch_autotune(teuk_batch* b, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out,
+                        int32_t* persistent_out);
+
+/* 0: every instance's current state is in its (phi, pi) as bound at step 0;
+ * 1: in (phi_next, pi_next).  Negative: error code. */
+int teuk_batch_current(teuk_batch* b);
+int teuk_batch_get_step(teuk_batch* b, int64_t* step);
+int teuk_batch_status(teuk_batch* b);
+const char* teuk_batch_last_error(teuk_batch* b);
+
 /* Scan the current state for non-finite values (synchronous).  Returns
  * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */
 int teuk_check_finite(teuk_ctx* ctx);

@@ -23,6 +23,13 @@ class TeukError(RuntimeError):
         super().__init__(f"{_strerror(code)}{': ' + msg if msg else ''}")
 
 
+class TeukDesc(ctypes.Structure):
+    _fields_ = [("grid", TeukGrid), ("a", ctypes.c_double), ("M", ctypes.c_double), ("m", ctypes.c_int32),
+                ("s", ctypes.c_int32), ("dt", ctypes.c_double), ("r0", ctypes.c_double), ("amp", ctypes.c_double),
+                ("sigma_r_cells", ctypes.c_double), ("sigma_th_cells", ctypes.c_double),
+                ("rstar_obs", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I32 = ctypes.c_int32
@@ -46,6 +53,19 @@ _SIGS = {
     "teuk_adjoint_workspace_bytes": (_I64, [_P]),
     "teuk_adjoint": (ctypes.c_int, [_P, _D, _P, _I64, _D, _P, _I64, _P, _P, ctypes.POINTER(_D),
                                     ctypes.POINTER(_D)]),
+    "teuk_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "teuk_batch_create": (ctypes.c_int, [_I32, ctypes.POINTER(TeukDesc), _I64, _P, ctypes.POINTER(_P)]),
+    "teuk_batch_destroy": (ctypes.c_int, [_P]),
+    "teuk_batch_bind": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I64]),
+    "teuk_batch_step": (ctypes.c_int, [_P, _I64]),
+    "teuk_batch_capture_graph": (ctypes.c_int, [_P, _I64]),
+    "teuk_batch_set_tiling": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "teuk_batch_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                           ctypes.POINTER(_I32)]),
+    "teuk_batch_current": (ctypes.c_int, [_P]),
+    "teuk_batch_get_step": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "teuk_batch_status": (ctypes.c_int, [_P]),
+    "teuk_batch_last_error": (ctypes.c_char_p, [_P]),
     "teuk_check_finite": (ctypes.c_int, [_P]),
     "teuk_status": (ctypes.c_int, [_P]),
     "teuk_last_error": (ctypes.c_char_p, [_P]),

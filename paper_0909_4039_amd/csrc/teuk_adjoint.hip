@@ -75,9 +75,7 @@ __device__ __forceinline__ AStage astage(const Rad<double>& q, const Ang<double>
 }
 
 // Unit-amplitude theta Gaussian of the source at a row (wave-uniform).
-__device__ __forceinline__ double load_gth(const double* __restrict__ ang, int row) {
-    return ang[(int64_t)row * A_STRIDE + A_GTH];
-}
+__device__ __forceinline__ double load_gth(const double* ang, int row) { return ang_at(ang, row, A_GTH); }
 
 // Source-gradient sums of one wave (see the file comment).
 struct GradAcc {

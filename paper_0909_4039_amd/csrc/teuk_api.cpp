@@ -69,14 +69,6 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
 
 size_t elem_size(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
 
-int default_rows(int nth, int kblock, int prec) {
-    // Measured on 32768 x 1024: single steps prefer short chunks (16 rows:
-    // many wavefronts, small tail); two fused steps need 4 halo rows per
-    // side and prefer 64 (FP32) to 96 (FP64) rows.
-    int rows = (kblock >= 2) ? (prec == 64 ? 96 : 64) : 16;
-    return std::min(rows, std::max(nth, 1));
-}
-
 int upload_tables(teuk_ctx* c) {
     const Geometry& g = c->geo;
     size_t nrad = g.rad_i.size(), nang = g.ang.size();
@@ -96,29 +88,8 @@ int upload_tables(teuk_ctx* c) {
     return TEUK_OK;
 }
 
-bool observer_index(const Geometry& g, double rstar_obs, int& i0, double& alpha) {
-    if (!(rstar_obs > g.rmin && rstar_obs < g.rmax)) return false;
-    int64_t i = (int64_t)std::floor((rstar_obs - g.rmin) / g.dr);
-    i = std::min<int64_t>(std::max<int64_t>(i, 0), g.nr - 2);
-    i0 = (int)i;
-    alpha = (rstar_obs - (g.rmin + double(i) * g.dr)) / g.dr;
-    return true;
-}
-
-int validate_phys(const teuk_grid* g, double a, double M, int32_t s) {
-    if (!g) return TEUK_EINVAL;
-    if (g->n_rstar < 4 || g->n_theta < 4) return TEUK_EINVAL;
-    if (g->n_rstar > (int64_t)1 << 26 || g->n_theta > (int64_t)1 << 20) return TEUK_EINVAL;
-    if ((int64_t)g->n_rstar * g->n_theta > ((int64_t)1 << 40)) return TEUK_EINVAL;
-    if (!(g->rstar_min < g->rstar_max) || !std::isfinite(g->rstar_min) || !std::isfinite(g->rstar_max))
-        return TEUK_EINVAL;
-    if (!(M > 0.0) || !(a >= 0.0) || !(a < M) || !std::isfinite(M)) return TEUK_EINVAL;
-    if (s < -2 || s > 2) return TEUK_EINVAL;
-    return TEUK_OK;
-}
-
 template <typename R>
-int launch_steps(teuk_ctx* c, int64_t n) {
+StepArgs<R> step_args(const teuk_ctx* c) {
     const Geometry& g = c->geo;
     StepArgs<R> a{};
     a.rad_i = (const R*)c->d_rad_i;
@@ -137,29 +108,46 @@ int launch_steps(teuk_ctx* c, int64_t n) {
     a.wave = (R*)c->wave;
     a.iobs = c->iobs;
     a.alpha = (R)c->alpha;
+    return a;
+}
+
+// One launch of kb steps from the state at step `step` in pair `src` into
+// pair 1 - src; the recorder writes the entering states' rows if `record`.
+template <typename R>
+int launch_one(teuk_ctx* c, StepArgs<R>& a, int kb, int src, int64_t step, bool record) {
+    const Geometry& g = c->geo;
+    const int so = WAVE - 2 * kb;   // valid output columns per strip
+    a.kb = kb;
+    a.n_strips = (int)((g.nr + so - 1) / so);
+    a.n_tiles = a.n_strips * a.n_chunks;
+    for (int q = 0; q < KB_MAX; ++q) {
+        double t = c->t0 + double(step + q - c->step0) * c->dt;
+        double w0 = g.m * c->Omega * t, w1 = g.m * c->Omega * (t + 0.5 * c->dt);
+        a.ph[2 * q][0] = (R)std::cos(w0);
+        a.ph[2 * q][1] = (R)(-std::sin(w0));
+        a.ph[2 * q + 1][0] = (R)std::cos(w1);
+        a.ph[2 * q + 1][1] = (R)(-std::sin(w1));
+        int64_t row = step + q - c->obs_step0;
+        a.wave_row[q] = (record && q < kb && c->wave && row >= 0 && row < c->wave_cap) ? row : -1;
+    }
+    a.phi = (const R*)c->buf[src][0];
+    a.pi = (const R*)c->buf[src][1];
+    a.phi_out = (R*)c->buf[1 - src][0];
+    a.pi_out = (R*)c->buf[1 - src][1];
+    if constexpr (std::is_same<R, double>::value) launch_step_fp64(a, c->stream);
+    else launch_step_fp32(a, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return TEUK_OK;
+}
+
+template <typename R>
+int launch_steps(teuk_ctx* c, int64_t n) {
+    const Geometry& g = c->geo;
+    StepArgs<R> a = step_args<R>(c);
     for (int64_t done = 0; done < n;) {
         const int kb = (c->kblock >= 2 && n - done >= 2) ? 2 : 1;
-        const int so = WAVE - 2 * kb;   // valid output columns per strip
-        a.kb = kb;
-        a.n_strips = (int)((g.nr + so - 1) / so);
-        a.n_tiles = a.n_strips * a.n_chunks;
-        for (int q = 0; q < KB_MAX; ++q) {
-            double t = c->t0 + double(c->step + q - c->step0) * c->dt;
-            double w0 = g.m * c->Omega * t, w1 = g.m * c->Omega * (t + 0.5 * c->dt);
-            a.ph[2 * q][0] = (R)std::cos(w0);
-            a.ph[2 * q][1] = (R)(-std::sin(w0));
-            a.ph[2 * q + 1][0] = (R)std::cos(w1);
-            a.ph[2 * q + 1][1] = (R)(-std::sin(w1));
-            int64_t row = c->step + q - c->obs_step0;
-            a.wave_row[q] = (q < kb && c->wave && row >= 0 && row < c->wave_cap) ? row : -1;
-        }
-        a.phi = (const R*)c->buf[c->cur][0];
-        a.pi = (const R*)c->buf[c->cur][1];
-        a.phi_out = (R*)c->buf[1 - c->cur][0];
-        a.pi_out = (R*)c->buf[1 - c->cur][1];
-        if constexpr (std::is_same<R, double>::value) launch_step_fp64(a, c->stream);
-        else launch_step_fp32(a, c->stream);
-        HIP_TRY(c, hipGetLastError());
+        int rc = launch_one<R>(c, a, kb, c->cur, c->step, true);
+        if (rc != TEUK_OK) return rc;
         c->cur = 1 - c->cur;
         c->step += kb;
         done += kb;
@@ -176,6 +164,33 @@ int launch_steps(teuk_ctx* c, int64_t n) {
         HIP_TRY(c, hipGetLastError());
     }
     return TEUK_OK;
+}
+
+// Seconds per step of `launches` trial launches at the context's current
+// tiling and blocking.  Every trial launch reads the current pair and writes
+// the other one, so the state, the step count and the waveform are left as
+// they were (the other pair is scratch between steps).
+template <typename R>
+int time_trial(teuk_ctx* c, int launches, double* sec_per_step) {
+    StepArgs<R> a = step_args<R>(c);
+    const int kb = c->kblock;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, TEUK_EDEVICE, "hipEventCreate failed");
+    }
+    int rc = launch_one<R>(c, a, kb, c->cur, c->step, false);   // warm-up
+    if (rc == TEUK_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, TEUK_EDEVICE, "event record");
+    for (int k = 0; rc == TEUK_OK && k < launches; ++k) rc = launch_one<R>(c, a, kb, c->cur, c->step, false);
+    if (rc == TEUK_OK && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, TEUK_EDEVICE, "event record");
+    float ms = 0.0f;
+    if (rc == TEUK_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(c, TEUK_EDEVICE, "event timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == TEUK_OK) *sec_per_step = 1e-3 * ms / double(launches * kb);
+    return rc;
 }
 
 // Blocks of the reverse sweep's launch grid: the larger of the one- and
@@ -366,7 +381,7 @@ int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, do
     c->sig_r = sigma_r_cells;
     c->sig_th = sigma_th_cells;
     c->rstar0 = rstar_of_delta(r0 - g.rp, g.a, g.M);
-    c->Omega = std::sqrt(g.M) / (std::pow(r0, 1.5) + g.a * std::sqrt(g.M));
+    c->Omega = orbit_omega(r0, g.a, g.M);
     c->has_src = true;
     build_source(g, c->rstar0, sigma_r_cells * g.dr, sigma_th_cells * g.dth, amp);
     return upload_tables(c);
@@ -467,6 +482,52 @@ int teuk_set_blocking(teuk_ctx* c, int32_t steps_per_launch) {
 }
 
 int teuk_get_blocking(teuk_ctx* c) { return c ? c->kblock : TEUK_EINVAL; }
+
+int teuk_autotune(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out) {
+    if (!c) return TEUK_EINVAL;
+    if (c->status != TEUK_OK) return c->status;
+    if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
+    if (launches_per_trial < 1 || launches_per_trial > 10000)
+        return fail(c, TEUK_EINVAL, "launches_per_trial must be 1..10000");
+    static const int kRows[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const int nth = (int)c->geo.nth;
+    const int keep_rows = c->rows, keep_kb = c->kblock, keep_order = c->order;
+    const bool keep_default = c->rows_default;
+    double best = 0.0;
+    int best_rows = keep_rows, best_kb = keep_kb;
+    c->order = 0;
+    for (int kb = 1; kb <= KB_MAX; ++kb) {
+        int prev = 0;
+        for (int r : kRows) {
+            const int rows = std::min(r, nth);
+            if (rows == prev) continue;   // candidates clipped to n_theta repeat
+            prev = rows;
+            c->rows = rows;
+            c->kblock = kb;
+            double sec = 0.0;
+            int rc = (c->prec == 64) ? time_trial<double>(c, launches_per_trial, &sec)
+                                     : time_trial<float>(c, launches_per_trial, &sec);
+            if (rc != TEUK_OK) {
+                c->rows = keep_rows;
+                c->kblock = keep_kb;
+                c->order = keep_order;
+                c->rows_default = keep_default;
+                return rc;
+            }
+            if (best == 0.0 || sec < best) {
+                best = sec;
+                best_rows = rows;
+                best_kb = kb;
+            }
+        }
+    }
+    c->rows = best_rows;
+    c->kblock = best_kb;
+    c->rows_default = false;
+    if (rows_out) *rows_out = best_rows;
+    if (kb_out) *kb_out = best_kb;
+    return TEUK_OK;
+}
 
 int teuk_get_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* order) {
     if (!c) return TEUK_EINVAL;

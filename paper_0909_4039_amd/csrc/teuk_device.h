@@ -195,9 +195,19 @@ struct Ang {
     R sin2, a2s2, cs, wp, wm, w0, agth;
 };
 
+// The angular table is read-only while kernels run: it is read through the
+// constant address space, so the wave-uniform row reads are scalar loads
+// whatever the compiler can prove about the pointer's origin.
 template <typename R>
-__device__ __forceinline__ Ang<R> load_ang(const R* __restrict__ ang, int row) {
-    const R* g = ang + (int64_t)row * A_STRIDE;
+__device__ __forceinline__ R ang_at(const R* ang, int row, int field) {
+    typedef __attribute__((address_space(4))) const R* cptr;
+    return ((cptr)ang)[(int64_t)row * A_STRIDE + field];
+}
+
+template <typename R>
+__device__ __forceinline__ Ang<R> load_ang(const R* ang, int row) {
+    typedef __attribute__((address_space(4))) const R* cptr;
+    const cptr g = (cptr)ang + (int64_t)row * A_STRIDE;
     Ang<R> a;
     a.sin2 = g[A_SIN2];
     a.a2s2 = g[A_A2S2];

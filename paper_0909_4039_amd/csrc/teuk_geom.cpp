@@ -160,4 +160,39 @@ double max_delta_over_sigma2(const Geometry& g) {
     return best;
 }
 
+
+// ----------------------------------------------------- shared host checks
+
+int default_rows(int nth, int kblock, int prec) {
+    // Measured on 32768 x 1024: single steps prefer short chunks (16 rows:
+    // many wavefronts, small tail); two fused steps need 4 halo rows per
+    // side and prefer 64 (FP32) to 96 (FP64) rows.
+    int rows = (kblock >= 2) ? (prec == 64 ? 96 : 64) : 16;
+    return std::min(rows, std::max(nth, 1));
+}
+
+bool observer_index(const Geometry& g, double rstar_obs, int& i0, double& alpha) {
+    if (!(rstar_obs > g.rmin && rstar_obs < g.rmax)) return false;
+    int64_t i = (int64_t)std::floor((rstar_obs - g.rmin) / g.dr);
+    i = std::min<int64_t>(std::max<int64_t>(i, 0), g.nr - 2);
+    i0 = (int)i;
+    alpha = (rstar_obs - (g.rmin + double(i) * g.dr)) / g.dr;
+    return true;
+}
+
+int validate_phys(const teuk_grid* g, double a, double M, int32_t s) {
+    if (!g) return TEUK_EINVAL;
+    if (g->n_rstar < 4 || g->n_theta < 4) return TEUK_EINVAL;
+    if (g->n_rstar > (int64_t)1 << 26 || g->n_theta > (int64_t)1 << 20) return TEUK_EINVAL;
+    if ((int64_t)g->n_rstar * g->n_theta > ((int64_t)1 << 40)) return TEUK_EINVAL;
+    if (!(g->rstar_min < g->rstar_max) || !std::isfinite(g->rstar_min) || !std::isfinite(g->rstar_max))
+        return TEUK_EINVAL;
+    if (!(M > 0.0) || !(a >= 0.0) || !(a < M) || !std::isfinite(M)) return TEUK_EINVAL;
+    if (s < -2 || s > 2) return TEUK_EINVAL;
+    return TEUK_OK;
+}
+
+// Angular frequency of the circular equatorial orbit at r0.
+double orbit_omega(double r0, double a, double M) { return std::sqrt(M) / (std::pow(r0, 1.5) + a * std::sqrt(M)); }
+
 }  // namespace teuk

@@ -68,6 +68,15 @@ void build_source(Geometry& g, double rstar0, double sr, double sth, double amp)
 double angular_bound(const Geometry& g);
 double max_delta_over_sigma2(const Geometry& g);
 
+// Default theta rows per wavefront tile for a grid of nth rows.
+int default_rows(int nth, int kblock, int prec);
+// Observer column i0 and weight alpha for r*_obs; false outside the open grid.
+bool observer_index(const Geometry& g, double rstar_obs, int& i0, double& alpha);
+// Argument checks shared by teuk_create, teuk_suggest_dt and teuk_batch_create.
+int validate_phys(const teuk_grid* g, double a, double M, int32_t s);
+// Omega = sqrt(M) / (r0^{3/2} + a sqrt(M)), circular equatorial orbit.
+double orbit_omega(double r0, double a, double M);
+
 // ------------------------------------------------------------------ kernels
 
 constexpr int KB_MAX = 2;   // steps fused per launch (temporal blocking)
@@ -125,6 +134,40 @@ struct AdjArgs {
     double* slots;        // [blocks][WG_WAVES][3] source-gradient partial sums
 };
 
+// One instance of a batch (FP64): its bound buffers, tables and constants.
+// Tiles are numbered instance by instance; first_tile[kb - 1] is the first
+// global tile of this instance for launches of kb steps.
+struct BatchInst {
+    double* buf[2][2];        // [pair][Phi, Pi], interleaved complex [nth][nr]
+    const double* rad_i;
+    const double* rad_h;
+    const double* ang;
+    const double* phase;      // [rows][4]: e^{-i m Omega t_k}, e^{-i m Omega (t_k + dt/2)}
+    double* wave;             // [wave_cap][nth] or NULL
+    int64_t wave_cap;
+    int64_t stride;
+    int32_t nr, nth, rows, iobs;
+    int32_t first_tile[KB_MAX];
+    double dt, hdt, inv_dr, m2ma, alpha;
+};
+
+// Device clock of a batch: steps taken and launches made (the launch
+// parity selects the pair that holds the current states).
+struct BatchClock {
+    int64_t step;
+    int64_t launches;
+};
+
+struct BatchArgs {
+    const BatchInst* inst;
+    const BatchClock* clock;
+    int32_t n_inst;
+    int32_t n_tiles;          // total tiles at this launch's kb
+    int32_t kb;
+    int32_t record;           // 0: recorder off (trial launches)
+    int32_t persistent;       // 1: resident grid walking the tile list; 0: one workgroup per tile
+};
+
 constexpr int WAVE = 64;
 constexpr int WG_WAVES = 4;
 
@@ -134,6 +177,10 @@ void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int io
                          hipStream_t s);
 void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs, float alpha,
                          hipStream_t s);
+void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s);
+void launch_batch_advance(BatchClock* clock, int kb, hipStream_t s);
+void launch_batch_extract(const BatchInst* inst, int n_inst, int max_nth, const BatchClock* clock, hipStream_t s);
+int batch_blocks_per_cu(int kb);
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s);
 void launch_adjoint_init(double* lp, double* lq, const double* g_row, int64_t n, int nr, int iobs, double alpha,
                          hipStream_t s);

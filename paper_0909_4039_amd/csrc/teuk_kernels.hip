@@ -146,7 +146,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     //      corrector's means and differences at c (time n+1/2)
     cx<R> phL = zero, Qh, dhP, dhQ;  // Qh, dhP, dhQ are read only by B2, whose rows are a subset
     if (P >= st.plo && P <= st.phi) {
-        const R wp = K.ang[(int64_t)P * A_STRIDE + A_P];
+        const R wp = ang_at(K.ang, P, A_P);
         cx<R> Lf = rfma(wp, pbL, st.pb_acc);
         cx<R> hQ = rfma(st.hD, Lf, st.hQp);
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     // ---- C: finish the corrector (Eq. 14) of row Q: its Pi
     okQ = (Q >= st.olo && Q < st.ohi);
     if (okQ) {
-        const R wp = K.ang[(int64_t)Q * A_STRIDE + A_P];
+        const R wp = ang_at(K.ang, Q, A_P);
         cx<R> Lf = rfma(wp, phL, st.ph_acc);
         outQ = K.keep * rfma(st.nD, Lf, st.nQp);
     }
@@ -189,58 +189,37 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     st.ph_prev = phL;
 }
 
-// KB Lax-Wendroff steps per launch (temporal blocking).  Stage k advances
-// u^{n+k} to u^{n+k+1}; the intermediate states never leave registers:
-// stage k+1 consumes row X of stage k's output once both its Phi (finished
-// one iteration earlier) and its Pi are final, two rows behind.  Each
-// stage's arithmetic per point is the same code as for KB = 1, so results
-// are bitwise identical to KB single steps.  A strip loses one valid column
-// per side and a chunk needs two more halo rows per side for each extra
-// stage.
-template <typename R, int KB>
-__global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi, const R* __restrict__ pi,
-                                                    R* __restrict__ phi_out, R* __restrict__ pi_out,
-                                                    const R* __restrict__ rad_i, const R* __restrict__ rad_h,
-                                                    const R* __restrict__ ang, R* __restrict__ wave,
-                                                    StepArgs<R> A) {
+// KB Lax-Wendroff steps over one tile (one wavefront's strip of r* columns
+// and its chunk of theta rows), the work unit of both the single-mode and
+// the batched kernel.  Stage k advances u^{n+k} to u^{n+k+1}; the
+// intermediate states never leave registers: stage k+1 consumes row X of
+// stage k's output once both its Phi (finished one iteration earlier) and
+// its Pi are final, two rows behind.  Each stage's arithmetic per point is
+// the same code as for KB = 1, so results are bitwise identical to KB
+// single steps whatever the tiling or batching.  A strip loses one valid
+// column per side and a chunk needs two more halo rows per side for each
+// extra stage.  `srad` is this wavefront's own LDS slice (no barrier).
+template <typename R, int KB, typename P>
+__device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __restrict__ pi,
+                                          R* __restrict__ phi_out, R* __restrict__ pi_out,
+                                          const R* __restrict__ rad_i, const R* __restrict__ rad_h,
+                                          const R* __restrict__ ang, R* __restrict__ wave, const P& A,
+                                          int strip, int chunk, R (*srad)[N_RAD_USED][WAVE]) {
     constexpr int SO = WAVE - 2 * KB;   // valid output columns per strip
     const int lane = threadIdx.x & (WAVE - 1);
-    // wave-uniform quantities: keep them in scalar registers
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    // A workgroup = WG_WAVES adjacent r* strips at the same theta chunk, so
-    // that every row access of the group is one contiguous 4 KiB (FP64)
-    // span.  Block order (a tuning choice): chunk-major lets the groups that
-    // run together on an XCD touch neighbouring columns of the same rows;
-    // group-major keeps a strip group's chunks together so their halo rows
-    // are served by L2.
-    const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    int chunk, grp;
-    if (A.order == 0) {  // chunk-major: concurrent groups read the same rows
-        chunk = blk / ngrp;
-        grp = blk - chunk * ngrp;
-    } else {             // group-major: adjacent chunks share their halo rows in L2
-        grp = blk / A.n_chunks;
-        chunk = blk - grp * A.n_chunks;
-    }
-    const int strip = grp * WG_WAVES + wid;
-    if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
-    const int nr = A.nr, nth = A.nth;
+    const int nr = A.nr(), nth = A.nth();
     const int c = strip * SO - KB + lane;
     // Lanes outside the grid read a clamped column: they feed only the
     // half points beyond the r* boundaries, whose outputs are the Dirichlet
     // zeros or are never stored.
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
-    // radial numerators of this wavefront's columns (each wavefront fills
-    // and reads only its own slice, so no barrier is needed)
-    __shared__ R srad_all[WG_WAVES][2][N_RAD_USED][WAVE];   // [wave][half/integer][field][lane]
-    R (*srad)[N_RAD_USED][WAVE] = srad_all[wid];
+    // radial numerators of this wavefront's columns
     for (int k = 0; k < 2 * N_RAD_USED; ++k) {
         const int loc = k / N_RAD_USED, f = k % N_RAD_USED;
-        srad[loc][f][lane] = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride + cu];
+        srad[loc][f][lane] = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
     }
-    const int j0 = chunk * A.rows;
-    const int jend = min(j0 + A.rows, nth);
+    const int j0 = chunk * A.rows();
+    const int jend = min(j0 + A.rows(), nth);
     const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
     const unsigned boff = cu * (unsigned)(2 * sizeof(R));          // byte offset of this lane's column
     const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(R));
@@ -250,13 +229,13 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     K.lane = lane;
     K.nth = nth;
     K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
-    K.idr = A.inv_dr;
-    K.dt = A.dt;
-    K.hdt = A.hdt;
-    K.m2ma = A.m2ma;
+    K.idr = A.inv_dr();
+    K.dt = A.dt();
+    K.hdt = A.hdt();
+    K.m2ma = A.m2ma();
     // recorder: the strip holding columns iobs and iobs+1 among its lanes
-    const bool rec = (A.iobs / SO == strip);
-    const int wl = A.iobs - strip * SO + KB;
+    const bool rec = (A.iobs() / SO == strip);
+    const int wl = A.iobs() - strip * SO + KB;
     const cx<R> zero = {R(0), R(0)};
 
     // stage k produces rows [j0 - 2(KB-1-k), jend + 2(KB-1-k)), clipped
@@ -288,9 +267,8 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
             const int Lk = L - 2 * k;   // stage k works two rows behind stage k-1
             cx<R> oP, oQ;
             bool okP, okQ;
-            const cx<R> ph0 = {A.ph[2 * k][0], A.ph[2 * k][1]};
-            const cx<R> ph1 = {A.ph[2 * k + 1][0], A.ph[2 * k + 1][1]};
-            pipe_iter(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row[k] : -1, wl, j0, jend, A.alpha, oP,
+            const cx<R> ph0 = A.ph(2 * k), ph1 = A.ph(2 * k + 1);
+            pipe_iter(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend, A.alpha(), oP,
                       okP, oQ, okQ);
             if (k == KB - 1) {
                 if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, oQ);
@@ -311,6 +289,57 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     }
 }
 
+// Per-tile constants of the single-mode kernel: its kernel argument (the
+// compiler reloads kernel arguments where that frees registers).
+template <typename R>
+struct ArgParams {
+    const StepArgs<R>& A;
+    __device__ int nr() const { return A.nr; }
+    __device__ int nth() const { return A.nth; }
+    __device__ int rows() const { return A.rows; }
+    __device__ int64_t stride() const { return A.stride; }
+    __device__ int iobs() const { return A.iobs; }
+    __device__ R dt() const { return A.dt; }
+    __device__ R hdt() const { return A.hdt; }
+    __device__ R inv_dr() const { return A.inv_dr; }
+    __device__ R m2ma() const { return A.m2ma; }
+    __device__ R alpha() const { return A.alpha; }
+    __device__ cx<R> ph(int i) const { return {A.ph[i][0], A.ph[i][1]}; }
+    __device__ int64_t wave_row(int k) const { return A.wave_row[k]; }
+};
+
+// Single-mode launch: one tile per wavefront, WG_WAVES adjacent strips of
+// the same theta chunk per workgroup.
+template <typename R, int KB>
+__global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi, const R* __restrict__ pi,
+                                                    R* __restrict__ phi_out, R* __restrict__ pi_out,
+                                                    const R* __restrict__ rad_i, const R* __restrict__ rad_h,
+                                                    const R* __restrict__ ang, R* __restrict__ wave,
+                                                    StepArgs<R> A) {
+    // wave-uniform quantities: keep them in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    // Every row access of a workgroup is one contiguous 4 KiB (FP64) span.
+    // Block order (a tuning choice): chunk-major lets the groups that run
+    // together on an XCD touch neighbouring columns of the same rows;
+    // group-major keeps a strip group's chunks together so their halo rows
+    // are served by L2.
+    const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    int chunk, grp;
+    if (A.order == 0) {  // chunk-major: concurrent groups read the same rows
+        chunk = blk / ngrp;
+        grp = blk - chunk * ngrp;
+    } else {             // group-major: adjacent chunks share their halo rows in L2
+        grp = blk / A.n_chunks;
+        chunk = blk - grp * A.n_chunks;
+    }
+    const int strip = grp * WG_WAVES + wid;
+    if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
+    __shared__ R srad_all[WG_WAVES][2][N_RAD_USED][WAVE];   // [wave][half/integer][field][lane]
+    const ArgParams<R> P{A};
+    step_tile<R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, srad_all[wid]);
+}
+
 template <typename R>
 static void launch_step(const StepArgs<R>& a, hipStream_t s) {
     int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
@@ -323,6 +352,143 @@ static void launch_step(const StepArgs<R>& a, hipStream_t s) {
 }
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step(a, s); }
 void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step(a, s); }
+
+// Batched launches: every instance of a batch advances kb steps in one
+// launch.  Tiles are numbered instance by instance; the step and the
+// current pair come from the batch's device clock, so a captured graph of
+// these launches replays correctly.  Each tile runs step_tile, so batched
+// results are bitwise identical to single-mode runs.  Descriptors and clock
+// are read-only during a launch and are read through the constant address
+// space (wave-uniform scalar loads).
+typedef __attribute__((address_space(4))) const BatchInst* cinst;
+typedef __attribute__((address_space(4))) const BatchClock* cclock;
+typedef __attribute__((address_space(4))) const double* cdbl;
+
+// Per-tile constants of a batched launch, read from the instance's
+// descriptor, phase table and the clock (constant memory: reloaded where
+// that frees registers).
+struct InstParams {
+    cinst I;
+    cclock clk;
+    int record;
+    __device__ int nr() const { return I->nr; }
+    __device__ int nth() const { return I->nth; }
+    __device__ int rows() const { return I->rows; }
+    __device__ int64_t stride() const { return I->stride; }
+    __device__ int iobs() const { return I->iobs; }
+    __device__ double dt() const { return I->dt; }
+    __device__ double hdt() const { return I->hdt; }
+    __device__ double inv_dr() const { return I->inv_dr; }
+    __device__ double m2ma() const { return I->m2ma; }
+    __device__ double alpha() const { return I->alpha; }
+    // i = 2 q + (0: t, 1: t + dt/2) for fused step q
+    __device__ cx<double> ph(int i) const {
+        const cdbl p = (cdbl)I->phase + 4 * (clk->step + (i >> 1)) + 2 * (i & 1);
+        return {p[0], p[1]};
+    }
+    __device__ int64_t wave_row(int q) const {
+        const int64_t row = clk->step + q;
+        return (record && I->wave != nullptr && row < I->wave_cap) ? row : -1;
+    }
+};
+
+template <int KB>
+__device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, int record,
+                                           double (*srad)[N_RAD_USED][WAVE]) {
+    constexpr int SO = WAVE - 2 * KB;
+    const InstParams P{I, clk, record};
+    const int src = (int)(clk->launches & 1);
+    const int n_strips = (I->nr + SO - 1) / SO;
+    const int ngrp = (n_strips + WG_WAVES - 1) / WG_WAVES;
+    const int local = t - I->first_tile[KB - 1];
+    const int chunk = local / ngrp;
+    const int strip = (local - chunk * ngrp) * WG_WAVES + wid;
+    if (strip < n_strips)
+        step_tile<double, KB>(I->buf[src][0], I->buf[src][1], I->buf[1 - src][0], I->buf[1 - src][1], I->rad_i,
+                              I->rad_h, I->ang, I->wave, P, strip, chunk, srad);
+}
+
+// Persistent form: the grid holds as many workgroups as stay resident and
+// the 8 XCDs each walk a contiguous range of the tile list, so strips that
+// share halo columns and rows stay in one L2.
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_kernel(BatchArgs B) {
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    const cinst insts = (cinst)B.inst;
+    const cclock clk = (cclock)B.clock;
+    const int X = 8;
+    const int x = blockIdx.x % X, kx = blockIdx.x / X, nbx = gridDim.x / X;
+    const int t_lo = (int)((int64_t)B.n_tiles * x / X), t_hi = (int)((int64_t)B.n_tiles * (x + 1) / X);
+    int i = 0;
+    for (int t = t_lo + kx; t < t_hi; t += nbx) {
+        while (i + 1 < B.n_inst && insts[i + 1].first_tile[KB - 1] <= t) ++i;
+        batch_tile<KB>(insts + i, clk, t, wid, B.record, srad_all[wid]);
+    }
+}
+
+// Grid form: one workgroup per tile (XCD-aware order); the instance is
+// found by bisection over the tiles' prefix.
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_grid_kernel(BatchArgs B) {
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    const cinst insts = (cinst)B.inst;
+    const cclock clk = (cclock)B.clock;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = B.n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (insts[mid].first_tile[KB - 1] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    batch_tile<KB>(insts + lo, clk, t, wid, B.record, srad_all[wid]);
+}
+
+int batch_blocks_per_cu(int kb) {
+    int n = 0;
+    hipError_t e = (kb == 2) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_batch_kernel<2>, WAVE * WG_WAVES, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_batch_kernel<1>, WAVE * WG_WAVES, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s) {
+    if (a.persistent) {
+        if (a.kb == 2) hipLaunchKernelGGL(lw_batch_kernel<2>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a);
+        else hipLaunchKernelGGL(lw_batch_kernel<1>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a);
+    } else {
+        if (a.kb == 2) hipLaunchKernelGGL(lw_batch_grid_kernel<2>, dim3(a.n_tiles), dim3(WAVE * WG_WAVES), 0, s, a);
+        else hipLaunchKernelGGL(lw_batch_grid_kernel<1>, dim3(a.n_tiles), dim3(WAVE * WG_WAVES), 0, s, a);
+    }
+}
+
+// The clock advances after each batched launch (one lane, vector store).
+__global__ void batch_advance_kernel(BatchClock* clock, int kb) {
+    if (threadIdx.x == 0) {
+        clock->step += kb;
+        clock->launches += 1;
+    }
+}
+void launch_batch_advance(BatchClock* clock, int kb, hipStream_t s) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, s, clock, kb);
+}
+
+// Waveform row of the current state of every recording instance (the row
+// of the step the clock shows), as the single-mode extract does.
+__global__ void batch_extract_kernel(const BatchInst* __restrict__ inst, const BatchClock* __restrict__ clock) {
+    const BatchInst* I = &inst[blockIdx.y];
+    const int64_t row = clock->step;
+    const int src = (int)(clock->launches & 1);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I->wave == nullptr || row >= I->wave_cap || j >= I->nth) return;
+    const double* phi = I->buf[src][0];
+    cx<double> p0 = ldc(phi, (int64_t)j * I->nr + I->iobs);
+    cx<double> p1 = ldc(phi, (int64_t)j * I->nr + I->iobs + 1);
+    stc(I->wave, row * I->nth + j, rfma(I->alpha, p1, (1.0 - I->alpha) * p0));
+}
+void launch_batch_extract(const BatchInst* inst, int n_inst, int max_nth, const BatchClock* clock, hipStream_t s) {
+    hipLaunchKernelGGL(batch_extract_kernel, dim3((max_nth + 255) / 256, n_inst), dim3(256), 0, s, inst, clock);
+}
 
 // Waveform at r*_obs: w_j = (1 - alpha) Phi_{i0,j} + alpha Phi_{i0+1,j}.
 template <typename R>

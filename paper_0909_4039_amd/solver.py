@@ -118,6 +118,16 @@ class Solver:
     def get_blocking(self):
         return check_int(_lib.lib().teuk_get_blocking(self._ctx))
 
+    def autotune(self, launches_per_trial=20):
+        """Pick the fastest (theta rows per wave, steps per launch) by timing
+        trial launches on the bound state; returns (rows, steps_per_launch).
+        Results of ``step`` are bitwise identical for every choice."""
+        r = ctypes.c_int32()
+        k = ctypes.c_int32()
+        check(_lib.lib().teuk_autotune(self._ctx, int(launches_per_trial), ctypes.byref(r), ctypes.byref(k)),
+              self._ctx)
+        return r.value, k.value
+
     def get_tiling(self):
         r = ctypes.c_int32()
         o = ctypes.c_int32()

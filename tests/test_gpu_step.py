@@ -253,3 +253,32 @@ def test_fp32_waveform_error(oracle_mod):
     err_s = rel(gp, op)
     print(f"[gpu] fp32 waveform rel err {err_w:.3e}, state {err_s:.3e}", flush=True)
     assert err_w <= 1e-5, err_w
+
+
+def test_autotune_keeps_state_and_results(oracle_mod):
+    import torch
+    from paper_0909_4039_amd.solver import Solver
+    case = dict(SMALL[4])
+    dt = _dt(oracle_mod, case)
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=77)
+    n = 25
+    ref = run_gpu(dict(case, dt=dt), phi, pi, n)
+    s = Solver(case["nr"], case["nth"], case["rmin"], case["rmax"], case["a"], 1.0, case["m"], case["s"], dt)
+    s.set_source(case["r0"], case["amp"])
+    s.set_state(phi, pi)
+    s.set_observer(case["robs"], n + 1)
+    s.step(5)
+    torch.cuda.synchronize()
+    before = (s.phi.clone(), s.pi.clone(), s.wave.clone(), s.get_time())
+    rows, kb = s.autotune(3)
+    print(f"[gpu] autotune picked rows={rows} kb={kb}", flush=True)
+    torch.cuda.synchronize()
+    assert torch.equal(s.phi, before[0]) and torch.equal(s.pi, before[1]) and torch.equal(s.wave, before[2])
+    assert s.get_time() == before[3]
+    assert s.get_tiling()[0] == rows and s.get_blocking() == kb
+    s.step(n - 5)
+    torch.cuda.synchronize()
+    got = (s.phi.cpu().numpy(), s.pi.cpu().numpy(), s.wave.cpu().numpy())
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    s.close()
