@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 BYTES_PER_UPDATE = {64: 64, 32: 32}   # read (Phi, Pi) + write (Phi', Pi'), complex
-KERNEL_SRC = os.path.join(ROOT, "paper_0909_4039_amd", "csrc", "teuk_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0909_4039_amd", "csrc", f) for f in ("teuk_kernels.hip", "teuk_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_traffic.json")
 
 
@@ -37,8 +37,10 @@ def measured_traffic(prec):
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if rec.get("kernel_sha256") != h:
+        h = hashlib.sha256()
+        for f in KERNEL_SRCS:
+            h.update(open(f, "rb").read())
+        if rec.get("kernel_sha256") != h.hexdigest():
             return None
         e = rec["fp%d" % prec]
         return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],
