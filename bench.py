@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-others", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
 
@@ -196,6 +197,75 @@ def time_batched(steps=200, graph_steps=20):
             "graph_steps": graph_steps}
 
 
+def time_small_and_mid():
+    """Two more single-mode workloads, each autotuned.
+
+    - Schwarzschild pulse, 256 x 64, 2000 steps: a launch-bound grid (16k
+      points), stepped by direct launches and as a batch of one replayed from
+      a captured HIP graph (bitwise identical results).
+    - Kerr a = 0.9 with source, 8192 x 256, 50000 steps, FP64 and FP32.
+    """
+    import torch
+    from paper_0909_4039_amd import inputs, workloads
+    from paper_0909_4039_amd.batch import Batch, make_desc
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    out = {}
+    W = workloads.SCHWARZSCHILD_PULSE
+    n = W.steps
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, n)
+    phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
+                           inputs.seeded_amplitude(W.pulse["seed"]))
+    s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt)
+    s.set_state(phi, pi)
+    rows, kb = s.autotune(20)
+    s.set_observer(W.rstar_obs, 2 * n + 1)
+    s.step(n // 10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.step(n)
+    torch.cuda.synchronize()
+    direct = time.perf_counter() - t
+    s.close()
+    b = Batch([make_desc(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.m, dt, s=W.s, rstar_obs=W.rstar_obs)],
+              2 * n)
+    b.set_state(0, phi, pi)
+    brows, bkb, bpers = b.autotune(20)
+    g = 200
+    b.capture_graph(g)
+    b.step(g)
+    b.synchronize()
+    t = time.perf_counter()
+    b.step(n)
+    b.synchronize()
+    graph = time.perf_counter() - t
+    b.close()
+    pts = W.nr * W.nth
+    out[W.name] = {"steps": n, "direct_us_per_step": direct / n * 1e6, "graph_us_per_step": graph / n * 1e6,
+                   "direct_updates_per_s": pts * n / direct, "graph_updates_per_s": pts * n / graph,
+                   "rows_per_wave": rows, "steps_per_launch": kb, "graph_steps": g}
+    W = workloads.KERR_SOURCE
+    n = W.steps
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, n)
+    res = {"steps": n}
+    for prec in (64, 32):
+        s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
+        s.set_source(W.r0, W.amp)
+        rows, kb = s.autotune(20)
+        s.set_observer(W.rstar_obs, n + 1)
+        s.step(100)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.step(n - 100)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        s.check_finite()
+        s.close()
+        res[f"fp{prec}"] = {"updates_per_s": W.nr * W.nth * (n - 100) / el, "rows_per_wave": rows,
+                            "steps_per_launch": kb}
+    out[W.name] = res
+    return out
+
+
 def cpu_baseline(W, seconds):
     import numpy as np
     import oracle
@@ -274,6 +344,8 @@ def main():
         out["adjoint"] = time_adjoint()
     if not args.no_batched:
         out["batched"] = time_batched()
+    if not args.no_others:
+        out["other_workloads"] = time_small_and_mid()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

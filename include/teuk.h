@@ -218,8 +218,9 @@ int teuk_batch_step(teuk_batch* b, int64_t n);
 /* Capture steps_per_graph steps (a positive multiple of the steps per
  * launch) as a HIP graph that teuk_batch_step replays; 0 drops the graph.
  * The kernels read the step and the current pair from a device-side
- * clock, so every replay continues where the last one stopped.  Changing
- * the tiling drops the graph. */
+ * clock plus per-launch offsets, and one clock advance ends each replay, so
+ * every replay continues where the last one stopped.  Changing the tiling
+ * drops the graph. */
 int teuk_batch_capture_graph(teuk_batch* b, int64_t steps_per_graph);
 
 /* Tile shape for every instance (rows clipped to each n_theta; 0: the

@@ -113,7 +113,8 @@ int grid_blocks(const teuk_batch* b, int kb) {
     return std::max(8, std::min(resident, need));
 }
 
-int launch(teuk_batch* b, int kb, bool record, bool advance) {
+// One launch of kb steps at (step, launch count) = clock + offsets.
+int launch(teuk_batch* b, int kb, bool record, int step_off, int launch_off) {
     BatchArgs a{};
     a.inst = b->d_inst;
     a.clock = b->d_clock;
@@ -122,12 +123,16 @@ int launch(teuk_batch* b, int kb, bool record, bool advance) {
     a.kb = kb;
     a.record = record ? 1 : 0;
     a.persistent = b->persistent;
+    a.step_off = step_off;
+    a.launch_off = launch_off;
     launch_batch_step(a, grid_blocks(b, kb), b->stream);
     BHIP(b, hipGetLastError());
-    if (advance) {
-        launch_batch_advance(b->d_clock, kb, b->stream);
-        BHIP(b, hipGetLastError());
-    }
+    return TEUK_OK;
+}
+
+int advance(teuk_batch* b, int steps, int launches) {
+    launch_batch_advance(b->d_clock, steps, launches, b->stream);
+    BHIP(b, hipGetLastError());
     return TEUK_OK;
 }
 
@@ -303,11 +308,19 @@ int teuk_batch_step(teuk_batch* b, int64_t n) {
             b->launches += b->graph_launches;
         }
     }
+    // the rest by direct launches at offsets from the clock, then one advance
+    // (in chunks, so that the offsets stay small)
     while (done < n) {
-        const int kb = (b->kblock >= 2 && n - done >= 2) ? 2 : 1;
-        if ((rc = launch(b, kb, true, true)) != TEUK_OK) return rc;
-        b->launches += 1;
-        done += kb;
+        int soff = 0, loff = 0;
+        while (done < n && soff < (1 << 20)) {
+            const int kb = (b->kblock >= 2 && n - done >= 2) ? 2 : 1;
+            if ((rc = launch(b, kb, true, soff, loff)) != TEUK_OK) return rc;
+            soff += kb;
+            loff += 1;
+            done += kb;
+        }
+        if ((rc = advance(b, soff, loff)) != TEUK_OK) return rc;
+        b->launches += loff;
     }
     b->step += n;
     int max_nth = 0;
@@ -329,7 +342,8 @@ int teuk_batch_capture_graph(teuk_batch* b, int64_t steps_per_graph) {
     if (rc != TEUK_OK) return rc;
     const int L = (int)(steps_per_graph / b->kblock);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < L && rc == TEUK_OK; ++k) rc = launch(b, b->kblock, true, true);
+    for (int k = 0; k < L && rc == TEUK_OK; ++k) rc = launch(b, b->kblock, true, k * b->kblock, k);
+    if (rc == TEUK_OK) rc = advance(b, L * b->kblock, L);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc != TEUK_OK || e != hipSuccess) {
@@ -385,9 +399,9 @@ int teuk_batch_autotune(teuk_batch* b, int32_t launches_per_trial, int32_t* rows
             if ((rc = layout(b)) != TEUK_OK || (rc = upload(b)) != TEUK_OK) break;
             // trial launches read the current pair and write the other one;
             // the clock does not move and the recorder is off
-            if ((rc = launch(b, kb, false, false)) != TEUK_OK) break;
+            if ((rc = launch(b, kb, false, 0, 0)) != TEUK_OK) break;
             if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = bfail(b, TEUK_EDEVICE, "event record"); break; }
-            for (int k = 0; k < launches_per_trial && rc == TEUK_OK; ++k) rc = launch(b, kb, false, false);
+            for (int k = 0; k < launches_per_trial && rc == TEUK_OK; ++k) rc = launch(b, kb, false, 0, 0);
             if (rc != TEUK_OK) break;
             float ms = 0.0f;
             if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -166,6 +166,8 @@ struct BatchArgs {
     int32_t kb;
     int32_t record;           // 0: recorder off (trial launches)
     int32_t persistent;       // 1: resident grid walking the tile list; 0: one workgroup per tile
+    int32_t step_off;         // this launch's step and launch count relative to the clock
+    int32_t launch_off;
 };
 
 constexpr int WAVE = 64;
@@ -178,7 +180,7 @@ void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int io
 void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs, float alpha,
                          hipStream_t s);
 void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s);
-void launch_batch_advance(BatchClock* clock, int kb, hipStream_t s);
+void launch_batch_advance(BatchClock* clock, int steps, int launches, hipStream_t s);
 void launch_batch_extract(const BatchInst* inst, int n_inst, int max_nth, const BatchClock* clock, hipStream_t s);
 int batch_blocks_per_cu(int kb);
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s);

@@ -355,8 +355,9 @@ void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step(a, 
 
 // Batched launches: every instance of a batch advances kb steps in one
 // launch.  Tiles are numbered instance by instance; the step and the
-// current pair come from the batch's device clock, so a captured graph of
-// these launches replays correctly.  Each tile runs step_tile, so batched
+// current pair are the batch's device clock plus the launch's offsets, so a
+// captured graph of launches followed by one clock advance replays
+// correctly.  Each tile runs step_tile, so batched
 // results are bitwise identical to single-mode runs.  Descriptors and clock
 // are read-only during a launch and are read through the constant address
 // space (wave-uniform scalar loads).
@@ -371,6 +372,7 @@ struct InstParams {
     cinst I;
     cclock clk;
     int record;
+    int step_off;
     __device__ int nr() const { return I->nr; }
     __device__ int nth() const { return I->nth; }
     __device__ int rows() const { return I->rows; }
@@ -383,21 +385,21 @@ struct InstParams {
     __device__ double alpha() const { return I->alpha; }
     // i = 2 q + (0: t, 1: t + dt/2) for fused step q
     __device__ cx<double> ph(int i) const {
-        const cdbl p = (cdbl)I->phase + 4 * (clk->step + (i >> 1)) + 2 * (i & 1);
+        const cdbl p = (cdbl)I->phase + 4 * (clk->step + step_off + (i >> 1)) + 2 * (i & 1);
         return {p[0], p[1]};
     }
     __device__ int64_t wave_row(int q) const {
-        const int64_t row = clk->step + q;
+        const int64_t row = clk->step + step_off + q;
         return (record && I->wave != nullptr && row < I->wave_cap) ? row : -1;
     }
 };
 
 template <int KB>
-__device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, int record,
+__device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, const BatchArgs& B,
                                            double (*srad)[N_RAD_USED][WAVE]) {
     constexpr int SO = WAVE - 2 * KB;
-    const InstParams P{I, clk, record};
-    const int src = (int)(clk->launches & 1);
+    const InstParams P{I, clk, B.record, B.step_off};
+    const int src = (int)((clk->launches + B.launch_off) & 1);
     const int n_strips = (I->nr + SO - 1) / SO;
     const int ngrp = (n_strips + WG_WAVES - 1) / WG_WAVES;
     const int local = t - I->first_tile[KB - 1];
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int i = 0;
     for (int t = t_lo + kx; t < t_hi; t += nbx) {
         while (i + 1 < B.n_inst && insts[i + 1].first_tile[KB - 1] <= t) ++i;
-        batch_tile<KB>(insts + i, clk, t, wid, B.record, srad_all[wid]);
+        batch_tile<KB>(insts + i, clk, t, wid, B, srad_all[wid]);
     }
 }
 
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         if (insts[mid].first_tile[KB - 1] <= t) lo = mid;
         else hi = mid - 1;
     }
-    batch_tile<KB>(insts + lo, clk, t, wid, B.record, srad_all[wid]);
+    batch_tile<KB>(insts + lo, clk, t, wid, B, srad_all[wid]);
 }
 
 int batch_blocks_per_cu(int kb) {
@@ -462,15 +464,15 @@ void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s) {
     }
 }
 
-// The clock advances after each batched launch (one lane, vector store).
-__global__ void batch_advance_kernel(BatchClock* clock, int kb) {
+// The clock advances after a run of batched launches (one lane, vector store).
+__global__ void batch_advance_kernel(BatchClock* clock, int steps, int launches) {
     if (threadIdx.x == 0) {
-        clock->step += kb;
-        clock->launches += 1;
+        clock->step += steps;
+        clock->launches += launches;
     }
 }
-void launch_batch_advance(BatchClock* clock, int kb, hipStream_t s) {
-    hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, s, clock, kb);
+void launch_batch_advance(BatchClock* clock, int steps, int launches, hipStream_t s) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, s, clock, steps, launches);
 }
 
 // Waveform row of the current state of every recording instance (the row
