@@ -62,9 +62,10 @@
  *
  * Parity status: the coefficient forms, the angular operator, the tortoise
  * map, the scheme's order of accuracy, the Schwarzschild l=2 ringdown, the
- * m -> -m mirror symmetry and the adjoint are pinned by tests.  Kerr
- * absolute values have no external reference (parity unpinned beyond the
- * invariants above).
+ * Kerr a = 0.5 l = m = 2 ringdown (which depends on every a-dependent
+ * coefficient), the m -> -m mirror symmetry and the adjoint are pinned by
+ * tests.  Kerr pointwise values have no printed reference; they are pinned
+ * through the Kerr ringdown and the invariants above.
  */
 #include <complex.h>
 #include <math.h>

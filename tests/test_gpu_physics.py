@@ -1,0 +1,65 @@
+"""Physics pins on the GPU path: waveforms computed by libteuk ring down at
+the l=2 quasinormal frequencies of tests/golden (Schwarzschild, and Kerr
+a = 0.5 on the co-rotating l = m = 2 branch), converging at second order
+under r* refinement.  Same set-up as the oracle's ringdown test (pulse at
+r* = 20 with the discrete l=2 profile, read at r* = 40, matrix-pencil fit
+in t in [100, 180] M), at finer grids than the oracle can afford.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_0909_4039_amd import inputs
+from test_oracle_qnm import pencil
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(__file__)
+SCHW = json.load(open(os.path.join(HERE, "golden", "schwarzschild_qnm_l2.json")))
+KERR = json.load(open(os.path.join(HERE, "golden", "kerr_qnm_l2m2_a0.5.json")))
+
+
+def gpu_ringdown(oracle_mod, nr, a, nth=32):
+    import torch
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    rmin, rmax = -100.0, 300.0
+    A = oracle_mod.angular_matrix(nth, 2, -2)      # input profile only
+    ev, V = np.linalg.eig(A)
+    k = np.argmin(np.abs(ev + 4.0))
+    Y = np.real(V[:, k])
+    Y /= Y[np.argmax(np.abs(Y))]
+    dt = suggest_dt(nr, nth, rmin, rmax, a, 1.0, 2, -2, 20000)
+    n = int(np.ceil(190.0 / dt))
+    rs, _ = inputs.grid(nr, nth, rmin, rmax)
+    g = np.exp(-(rs - 20.0) ** 2 / 32.0)
+    phi = (Y[:, None] * g[None, :]).astype(complex)
+    pi = (Y[:, None] * (-(rs - 20.0) / 16.0 * g)[None, :]).astype(complex)
+    s = Solver(nr, nth, rmin, rmax, a, 1.0, 2, -2, dt)
+    s.set_state(phi, pi)
+    s.set_observer(40.0, n + 1)
+    s.autotune(5)
+    s.step(n)
+    torch.cuda.synchronize()
+    s.check_finite()
+    w = s.wave.cpu().numpy()
+    s.close()
+    t = np.arange(n + 1) * dt
+    sel = (t >= 100.0) & (t <= 180.0)
+    stride = max(1, int(0.25 / dt))
+    y = w[sel, nth // 2][::stride]
+    om = pencil(y.real if a == 0.0 else y, dt * stride)
+    return om[np.argmax(om.real)]
+
+
+@pytest.mark.parametrize("gold", [SCHW, KERR], ids=["schwarzschild", "kerr_a0.5"])
+def test_gpu_ringdown_frequency(oracle_mod, gold):
+    a = gold.get("a", 0.0)
+    w1 = gpu_ringdown(oracle_mod, 1025, a)
+    w2 = gpu_ringdown(oracle_mod, 2049, a)
+    wx = w2 + (w2 - w1) / 3.0
+    ref = gold["omega_re"] + 1j * gold["omega_im"]
+    print(f"[gpu] a={a}: 1025 -> {w1:.5f}, 2049 -> {w2:.5f}, extrapolated {wx:.5f}, reference {ref}", flush=True)
+    assert abs(w2.real - ref.real) < 0.005 * ref.real and abs(w2.imag - ref.imag) < 0.03 * abs(ref.imag)
+    assert abs(wx.real - ref.real) < 0.005 * ref.real and abs(wx.imag - ref.imag) < 0.01 * abs(ref.imag)
