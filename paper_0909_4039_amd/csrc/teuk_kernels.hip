@@ -44,6 +44,9 @@ namespace teuk {
 //   Phi' = f0 + tau (g - b df)                         (complete)
 //   Pi'  = g0 + tau (b dg + T - y^2 [...])             (without the angular term)
 //   D    = tau Delta y^2                               (weight of Lth Phi)
+// The differences arrive unscaled (u_{i+1} - u_i): 1/dr* is folded into b
+// (one multiply) and into CR (the radial fields CRR and WBN are scaled when
+// the tile loads them, and m2ma_idr = -2 m a / dr*).
 template <typename R>
 struct Stage {
     cx<R> phi, pi_part;
@@ -51,21 +54,21 @@ struct Stage {
 };
 
 template <typename R>
-__device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2ma, R tau, cx<R> ph,
+__device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2ma_idr, R idr, R tau, cx<R> ph,
                                           cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df, cx<R> dg) {
     R S2 = fma(q.w2, q.w2, -g.a2s2 * q.del);   // Sigma^2
     R y = rsqrt_full(S2);                      // 1/Sigma
     R y2 = y * y;
-    R b = q.w2 * y;                            // b, Eq. (6)
-    cx<R> X = {fma(-b, df.re, gm.re), fma(-b, df.im, gm.im)};          // Pi - b dPhi
-    cx<R> CR = {fma(q.wbn * g.sin2, y2, q.crr), m2ma * q.w2};
+    R bi = (q.w2 * y) * idr;                   // b / dr*, Eq. (6)
+    cx<R> X = {fma(-bi, df.re, gm.re), fma(-bi, df.im, gm.im)};        // Pi - b dPhi
+    cx<R> CR = {fma(q.wbn * g.sin2, y2, q.crr), m2ma_idr * q.w2};     // CR / dr*
     cx<R> CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
     cx<R> V = {q.vr, q.vi};
     cx<R> acc = cfma(CR, df, cfma(V, f, cmul(CT, X)));
     cx<R> T = (g.agth * q.gr) * ph;
     Stage<R> o;
     o.phi = {fma(tau, X.re, f0.re), fma(tau, X.im, f0.im)};
-    cx<R> rhs = {fma(b, dg.re, fma(-y2, acc.re, T.re)), fma(b, dg.im, fma(-y2, acc.im, T.im))};
+    cx<R> rhs = {fma(bi, dg.re, fma(-y2, acc.re, T.re)), fma(bi, dg.im, fma(-y2, acc.im, T.im))};
     o.pi_part = {fma(tau, rhs.re, g0.re), fma(tau, rhs.im, g0.im)};
     o.dw = tau * q.del * y2;
     return o;
@@ -112,7 +115,7 @@ struct Consts {
     const R* ang;
     const R (*srad)[N_RAD_USED][WAVE];
     int lane, nth;
-    R keep, idr, dt, hdt, m2ma;
+    R keep, idr, dt, hdt, m2ma_idr;
 };
 
 // One iteration of a stage at its row index L with input row L = (p, q).
@@ -136,8 +139,8 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
         cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
         pbL = half * (p + p1);
         Qb = half * (q + q1);
-        dP = K.idr * (p1 - p);
-        dQ = K.idr * (q1 - q);
+        dP = p1 - p;             // unscaled: 1/dr* is folded into the stage
+        dQ = q1 - q;
         if (wrow >= 0 && L >= rlo && L < rhi) {
             if (K.lane == wl) stc(wave, wrow * K.nth + L, rfma(alpha, p1, (R(1) - alpha) * p));
         }
@@ -152,15 +155,15 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
         phL = half * (st.hP + hPm);
         Qh = half * (hQ + hQm);
-        dhP = K.idr * (st.hP - hPm);
-        dhQ = K.idr * (hQ - hQm);
+        dhP = st.hP - hPm;
+        dhQ = hQ - hQm;
     }
     // ---- A2: non-angular part of the predictor of half row L and the
     //      bracket of its stencil
     if (L >= st.plo && L <= st.phi) {
         const Ang<R> g = load_ang(K.ang, L);
         const Rad<R> qh = lds_rad<R>(K.srad[0], K.lane);   // half point c+1/2
-        Stage<R> o = stage(qh, g, K.m2ma, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
+        Stage<R> o = stage(qh, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
         st.hP = o.phi;
         st.hQp = o.pi_part;
         st.hD = o.dw;
@@ -180,7 +183,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     if (okP) {
         const Ang<R> g = load_ang(K.ang, P);
         const Rad<R> qi = lds_rad<R>(K.srad[1], K.lane);   // integer point c
-        Stage<R> o = stage(qi, g, K.m2ma, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
+        Stage<R> o = stage(qi, g, K.m2ma_idr, K.idr, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
         st.nQp = o.pi_part;
         st.nD = o.dw;
         outP = K.keep * o.phi;
@@ -213,10 +216,13 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     // half points beyond the r* boundaries, whose outputs are the Dirichlet
     // zeros or are never stored.
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
-    // radial numerators of this wavefront's columns
+    // radial numerators of this wavefront's columns (CRR and WBN, which
+    // multiply r* differences only, carry the 1/dr* of those differences)
+    const R idr = A.inv_dr();
     for (int k = 0; k < 2 * N_RAD_USED; ++k) {
         const int loc = k / N_RAD_USED, f = k % N_RAD_USED;
-        srad[loc][f][lane] = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
+        const R v = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
+        srad[loc][f][lane] = (f == R_CRR || f == R_WBN) ? v * idr : v;
     }
     const int j0 = chunk * A.rows();
     const int jend = min(j0 + A.rows(), nth);
@@ -229,10 +235,10 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     K.lane = lane;
     K.nth = nth;
     K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
-    K.idr = A.inv_dr();
+    K.idr = idr;
     K.dt = A.dt();
     K.hdt = A.hdt();
-    K.m2ma = A.m2ma();
+    K.m2ma_idr = A.m2ma() * idr;
     // recorder: the strip holding columns iobs and iobs+1 among its lanes
     const bool rec = (A.iobs() / SO == strip);
     const int wl = A.iobs() - strip * SO + KB;
