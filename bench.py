@@ -263,6 +263,23 @@ def time_small_and_mid():
         res[f"fp{prec}"] = {"updates_per_s": W.nr * W.nth * (n - 100) / el, "rows_per_wave": rows,
                             "steps_per_launch": kb}
     out[W.name] = res
+    # the same grid with the particle inspiralling (mass ratio 1e-4) from r0 = 10
+    from paper_0909_4039_amd import inputs as _inputs
+    s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt)
+    s.set_source(W.r0, W.amp)
+    s.set_trajectory(_inputs.inspiral_trajectory(W.r0, W.a, W.M, 1e-4, dt, n))
+    rows, kb = s.autotune(20)
+    s.set_observer(W.rstar_obs, n + 1)
+    s.step(100)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.step(n - 100)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    s.check_finite()
+    s.close()
+    out[W.name + "_inspiral"] = {"steps": n, "mass_ratio": 1e-4, "fp64_updates_per_s": W.nr * W.nth * (n - 100) / el,
+                                 "rows_per_wave": rows, "steps_per_launch": kb}
     return out
 
 

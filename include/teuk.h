@@ -85,6 +85,19 @@ int teuk_bind_state(teuk_ctx* ctx, void* phi, void* pi, void* phi_next, void* pi
 int teuk_set_source(teuk_ctx* ctx, double r0, double amp, double sigma_r_cells,
                     double sigma_th_cells);
 
+/* Moving source (an inspiralling particle, as in the waveform of the paper's
+ * Fig. 1): from the current step on, the source of teuk_set_source (its
+ * amplitude and widths) follows the orbit r0_phase, a host array of n_half
+ * pairs (r0, phi) giving the orbit radius and phase at t_now + k dt/2,
+ * k = 0 .. n_half - 1 (copied).  Step s after this call uses entry 2s at
+ * t^n (predictor: centre r*(r0), phase e^{-i m phi}) and entry 2s + 1 at
+ * t^n + dt/2 (corrector); teuk_step fails with TEUK_EINVAL past the table.
+ * With r0 fixed and phi = Omega t it is the fixed-orbit source up to
+ * rounding.  r0_phase = NULL returns to the fixed orbit.  Requires
+ * teuk_set_source first (TEUK_ESTATE) and r0 > r+ in every entry.  The
+ * reverse sweep refuses a context with a trajectory (TEUK_ENOTSUP). */
+int teuk_set_trajectory(teuk_ctx* ctx, const double* r0_phase, int64_t n_half);
+
 /* Waveform recorder: from now on each step records
  * w_j = (1 - alpha) Phi_{i0,j} + alpha Phi_{i0+1,j}, r*_obs = r*_{i0} + alpha dr*,
  * into wave[k][n_theta] (device, complex, caller-owned) where k counts

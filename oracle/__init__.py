@@ -80,6 +80,7 @@ def _L():
             "teuko_dr": (D, [P]), "teuko_dth": (D, [P]), "teuko_rstar0": (D, [P]),
             "teuko_Omega": (D, [P]), "teuko_iobs": (I64, [P]), "teuko_alpha": (D, [P]),
             "teuko_max_DoS2": (D, [P]),
+            "teuko_set_trajectory": (ctypes.c_int, [P, P, I64, D]),
             "teuko_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -172,11 +173,23 @@ class Oracle:
         assert x.shape == self.shape, (x.shape, self.shape)
         return x
 
+    def set_trajectory(self, r0_phi, t0=0.0):
+        """Moving source: r0_phi[k] = (r0, phi) at t = t0 + k dt/2 (None: static source)."""
+        if r0_phi is None:
+            _L().teuko_set_trajectory(self._c, None, 0, 0.0)
+            self._traj = None
+            return
+        self._traj = np.ascontiguousarray(r0_phi, dtype=np.float64)
+        assert self._traj.ndim == 2 and self._traj.shape[1] == 2
+        if _L().teuko_set_trajectory(self._c, _ptr(self._traj), self._traj.shape[0], float(t0)) != 0:
+            raise ValueError("oracle: invalid trajectory")
+
     def step(self, phi, pi, t):
         """One Lax-Wendroff step (Eqs. 13-14) from time t."""
         phi, pi = self._arr(phi), self._arr(pi)
         o1, o2 = np.empty_like(phi), np.empty_like(pi)
-        _L().teuko_step(self._c, _ptr(phi), _ptr(pi), _ptr(o1), _ptr(o2), float(t))
+        if _L().teuko_step(self._c, _ptr(phi), _ptr(pi), _ptr(o1), _ptr(o2), float(t)) != 0:
+            raise ValueError("oracle: step outside the trajectory table")
         return o1, o2
 
     def extract(self, phi):

@@ -50,6 +50,11 @@
  *     stand-in is a unit-peak Gaussian in (r*, theta) centred on r*(r0) and
  *     theta = pi/2, times e^{-i m Omega t}, with Omega = sqrt(M)/(r0^{3/2} + a sqrt(M)),
  *     added to the Pi row of S.
+ *   - Moving source (an inspiral, as in the paper's Fig. 1): the orbit is
+ *     given as input, a table of (r0, phi) at every half step; the source
+ *     is the same Gaussian centred on r*(r0(t)) with phase e^{-i m phi(t)},
+ *     evaluated at t^n (predictor) and t^n + dt/2 (corrector).  With
+ *     phi = Omega t and r0 fixed it is the static source.
  *   - Waveform: linear interpolation of Phi in r* at r*_obs, for every theta.
  *   - Adjoint: the exact transpose of one step in the real 4-component view
  *     (Eq. 9), written out by hand in reverse order, and the source-parameter
@@ -189,6 +194,10 @@ typedef struct {
     /* work */
     cplx *Pb, *Qb, *dP, *dQ, *LP, *hP, *hQ;
     int64_t iobs; double alpha; /* observer: column (full grid) and weight     */
+    /* moving source: (r0, phi) at t = traj_t0 + k dt/2, k < traj_n (NULL: static) */
+    double* traj;
+    int64_t traj_n;
+    double traj_t0;
 } teuko_ctx;
 
 static double theta_of(const teuko_ctx* c, int64_t J) { return (J + 0.5) * c->dth; }
@@ -196,6 +205,7 @@ static double theta_of(const teuko_ctx* c, int64_t J) { return (J + 0.5) * c->dt
 void teuko_destroy(teuko_ctx* c) {
     if (!c) return;
     free(c->th); free(c->ci); free(c->ch); free(c->gi); free(c->gh); free(c->xi); free(c->xh);
+    free(c->traj);
     free(c->Pb); free(c->Qb); free(c->dP); free(c->dQ); free(c->LP); free(c->hP); free(c->hQ);
     free(c);
 }
@@ -324,6 +334,36 @@ static cplx col_nb(const teuko_ctx* c, const cplx* f, int64_t jj, int64_t ii, in
     return f[jj * c->p.ni + k];
 }
 
+/* Moving source: set the orbit table (copied).  Entry k holds (r0, phi) at
+   t = t0 + k dt/2.  NULL clears it.  Returns -1 for an invalid table. */
+int teuko_set_trajectory(teuko_ctx* c, const double* r0_phi, int64_t n_half, double t0) {
+    free(c->traj);
+    c->traj = NULL;
+    c->traj_n = 0;
+    if (!r0_phi) return 0;
+    double rp, rm;
+    horizons(c->p.a, c->p.M, &rp, &rm);
+    if (n_half < 2) return -1;
+    for (int64_t k = 0; k < n_half; ++k)
+        if (!(r0_phi[2 * k] > rp) || !isfinite(r0_phi[2 * k + 1])) return -1;
+    c->traj = (double*)malloc(sizeof(double) * 2 * n_half);
+    memcpy(c->traj, r0_phi, sizeof(double) * 2 * n_half);
+    c->traj_n = n_half;
+    c->traj_t0 = t0;
+    return 0;
+}
+
+/* T at column ii, row jj of a point at r* = xs for an orbit at (r0, phi):
+   amp exp(-(r* - r*(r0))^2 / (2 sr^2)) exp(-(th - pi/2)^2 / (2 sth^2)) e^{-i m phi}. */
+static cplx moving_T(const teuko_ctx* c, double xs, int64_t jj, double r0, double phi) {
+    const teuko_params* p = &c->p;
+    double sr = p->sigma_r_cells * c->dr, st = p->sigma_th_cells * c->dth;
+    double x = xs - teuko_rstar_of_r(r0, p->a, p->M);
+    double th = c->th[jj];
+    double gth = exp(-(th - 0.5 * M_PI) * (th - 0.5 * M_PI) / (2.0 * st * st));
+    return p->amp * (exp(-x * x / (2.0 * sr * sr)) * gth) * cexp(-I * (double)p->m * phi);
+}
+
 int teuko_step(teuko_ctx* c, const double* phi_ri, const double* pi_ri,
                double* phi_out_ri, double* pi_out_ri, double t) {
     const teuko_params* p = &c->p;
@@ -334,6 +374,15 @@ int teuko_step(teuko_ctx* c, const double* phi_ri, const double* pi_ri,
     int64_t ni = p->ni, nj = p->nj;
     double dt = p->dt, dr = c->dr;
     cplx ph0 = phase(c, t), ph1 = phase(c, t + 0.5 * dt);
+    /* moving source: table entries at t (predictor) and t + dt/2 (corrector) */
+    const double* oa = NULL;
+    const double* ob = NULL;
+    if (c->traj) {
+        int64_t k = llround((t - c->traj_t0) / (0.5 * dt));
+        if (k < 0 || k + 1 >= c->traj_n) return -1;
+        oa = c->traj + 2 * k;
+        ob = c->traj + 2 * (k + 1);
+    }
 
     /* predictor, Eq. (13): half points ii+1/2 (index ii), time n+1/2 */
     #pragma omp parallel for schedule(static)
@@ -353,7 +402,8 @@ int teuko_step(teuko_ctx* c, const double* phi_ri, const double* pi_ri,
             int64_t k = jj * ni + ii;
             const coeffs* q = &c->ch[k];
             cplx L = angular_at(c, c->Pb + ii, ni, jj);
-            cplx T = p->amp * c->gh[k] * ph0;
+            cplx T = oa ? moving_T(c, p->rstar_min + (p->i0 + ii + 0.5) * dr, jj, oa[0], oa[1])
+                        : p->amp * c->gh[k] * ph0;
             cplx SPhi = c->Qb[k];
             cplx SPi = T - q->mu * c->dP[k] + q->DoS2 * L - q->V * c->Pb[k] - q->ct * c->Qb[k];
             c->hP[k] = c->Pb[k] - 0.5 * dt * (q->b * c->dP[k] - SPhi);
@@ -378,7 +428,8 @@ int teuko_step(teuko_ctx* c, const double* phi_ri, const double* pi_ri,
             if (Ig == 0 || Ig == p->nr - 1) { Phi1[k] = 0.0; Pi1[k] = 0.0; continue; }
             const coeffs* q = &c->ci[k];
             cplx L = angular_at(c, c->Pb + ii, ni, jj);
-            cplx T = p->amp * c->gi[k] * ph1;
+            cplx T = ob ? moving_T(c, p->rstar_min + (p->i0 + ii) * dr, jj, ob[0], ob[1])
+                        : p->amp * c->gi[k] * ph1;
             cplx SPhi = c->Qb[k];
             cplx SPi = T - q->mu * c->dP[k] + q->DoS2 * L - q->V * c->Pb[k] - q->ct * c->Qb[k];
             Phi1[k] = Phi[k] - dt * (q->b * c->dP[k] - SPhi);
@@ -408,7 +459,10 @@ int teuko_run(teuko_ctx* c, double* phi_ri, double* pi_ri, int64_t n, double t_s
     double* b1 = (double*)malloc(sizeof(cplx) * N);
     if (wave_ri && teuko_extract(c, phi_ri, wave_ri) != 0) { free(a1); free(b1); return -1; }
     for (int64_t k = 0; k < n; ++k) {
-        teuko_step(c, phi_ri, pi_ri, a1, b1, t_start + (double)k * c->p.dt);
+        if (teuko_step(c, phi_ri, pi_ri, a1, b1, t_start + (double)k * c->p.dt) != 0) {
+            free(a1); free(b1);
+            return -1;
+        }
         memcpy(phi_ri, a1, sizeof(cplx) * N);
         memcpy(pi_ri, b1, sizeof(cplx) * N);
         if (wave_ri) teuko_extract(c, phi_ri, wave_ri + 2 * (k + 1) * c->p.nj);
@@ -573,6 +627,8 @@ static void source_grad_add(const teuko_ctx* c, const cplx* a, int half, double 
    needs no forward states. */
 int teuko_adjoint_run(teuko_ctx* c, const double* g_ri, int64_t n, double t_start,
                       double* dphi0_ri, double* dpi0_ri, double* dL_dr0, double* dL_damp) {
+    /* the source-parameter gradients are those of the static source */
+    if (c->traj) return -1;
     const teuko_params* p = &c->p;
     int64_t ni = p->ni, nj = p->nj, N = ni * nj;
     const cplx* g = (const cplx*)g_ri;

@@ -41,6 +41,7 @@ _SIGS = {
     "teuk_bind_state": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "teuk_set_source": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "teuk_set_observer": (ctypes.c_int, [_P, _D, _P, _I64]),
+    "teuk_set_trajectory": (ctypes.c_int, [_P, _P, _I64]),
     "teuk_step": (ctypes.c_int, [_P, _I64]),
     "teuk_extract": (ctypes.c_int, [_P, _D, _P]),
     "teuk_get_time": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),

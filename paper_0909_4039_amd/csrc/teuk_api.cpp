@@ -38,6 +38,9 @@ struct teuk_ctx {
     // time: t = t0 + (step - step0) dt
     double t0 = 0;
     int64_t step0 = 0, step = 0;
+    // moving source: (r0, phi) at t(traj_step0) + k dt/2, k < traj_n
+    std::vector<double> traj;
+    int64_t traj_n = 0, traj_step0 = 0;
     // tiling
     int rows = 0;
     int order = 0;
@@ -108,6 +111,11 @@ StepArgs<R> step_args(const teuk_ctx* c) {
     a.wave = (R*)c->wave;
     a.iobs = c->iobs;
     a.alpha = (R)c->alpha;
+    a.moving = c->traj_n > 0 ? 1 : 0;
+    const double sr = c->sig_r * g.dr;
+    a.two_sr2 = (R)(2.0 * sr * sr);
+    a.rmin = (R)g.rmin;
+    a.dr = (R)g.dr;
     return a;
 }
 
@@ -123,6 +131,16 @@ int launch_one(teuk_ctx* c, StepArgs<R>& a, int kb, int src, int64_t step, bool 
     for (int q = 0; q < KB_MAX; ++q) {
         double t = c->t0 + double(step + q - c->step0) * c->dt;
         double w0 = g.m * c->Omega * t, w1 = g.m * c->Omega * (t + 0.5 * c->dt);
+        if (c->traj_n > 0) {
+            // moving source: orbit entries at t (predictor) and t + dt/2 (corrector)
+            int64_t k = 2 * (step + q - c->traj_step0);
+            k = std::min<int64_t>(std::max<int64_t>(k, 0), c->traj_n - 2);   // q >= kb: unused
+            const double* e = &c->traj[2 * k];
+            a.rs0[2 * q] = (R)rstar_of_delta(e[0] - g.rp, g.a, g.M);
+            a.rs0[2 * q + 1] = (R)rstar_of_delta(e[2] - g.rp, g.a, g.M);
+            w0 = g.m * e[1];
+            w1 = g.m * e[3];
+        }
         a.ph[2 * q][0] = (R)std::cos(w0);
         a.ph[2 * q][1] = (R)(-std::sin(w0));
         a.ph[2 * q + 1][0] = (R)std::cos(w1);
@@ -387,6 +405,24 @@ int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, do
     return upload_tables(c);
 }
 
+int teuk_set_trajectory(teuk_ctx* c, const double* r0_phase, int64_t n_half) {
+    if (!c) return TEUK_EINVAL;
+    if (!r0_phase) {
+        c->traj.clear();
+        c->traj_n = 0;
+        return TEUK_OK;
+    }
+    if (!c->has_src) return fail(c, TEUK_ESTATE, "teuk_set_source must come first (amplitude and widths)");
+    if (n_half < 2 || n_half > ((int64_t)1 << 34)) return fail(c, TEUK_EINVAL, "n_half must be 2..2^34");
+    for (int64_t k = 0; k < n_half; ++k)
+        if (!(r0_phase[2 * k] > c->geo.rp) || !std::isfinite(r0_phase[2 * k]) || !std::isfinite(r0_phase[2 * k + 1]))
+            return fail(c, TEUK_EINVAL, "orbit entry %lld: r0 must exceed r+ and both values be finite", (long long)k);
+    c->traj.assign(r0_phase, r0_phase + 2 * n_half);
+    c->traj_n = n_half;
+    c->traj_step0 = c->step;
+    return TEUK_OK;
+}
+
 int teuk_set_observer(teuk_ctx* c, double rstar_obs, void* wave, int64_t capacity_rows) {
     if (!c) return TEUK_EINVAL;
     if (!wave) {
@@ -414,6 +450,14 @@ int teuk_step(teuk_ctx* c, int64_t n) {
     if (n < 0) return fail(c, TEUK_EINVAL, "negative step count");
     if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
     if (n == 0 && !c->wave) return TEUK_OK;
+    if (c->traj_n > 0) {
+        const int64_t s0 = c->step - c->traj_step0;
+        // step s (counted from the call) reads entries 2s and 2s + 1
+        if (s0 < 0 || (n > 0 && 2 * (s0 + n) > c->traj_n))
+            return fail(c, TEUK_EINVAL, "steps %lld..%lld since the trajectory was set need %lld orbit entries, "
+                        "it has %lld", (long long)s0, (long long)(s0 + n - 1), (long long)(2 * (s0 + n)),
+                        (long long)c->traj_n);
+    }
     if (c->prec == 64) return launch_steps<double>(c, n);
     return launch_steps<float>(c, n);
 }
@@ -548,6 +592,7 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
     if (!c) return TEUK_EINVAL;
     if (c->status != TEUK_OK) return c->status;
     if (c->prec != TEUK_FP64) return fail(c, TEUK_ENOTSUP, "the reverse sweep is FP64 only");
+    if (c->traj_n > 0) return fail(c, TEUK_ENOTSUP, "the reverse sweep needs a fixed orbit (no trajectory)");
     if (n_steps < 0) return fail(c, TEUK_EINVAL, "negative step count");
     if (!std::isfinite(t_start)) return fail(c, TEUK_EINVAL, "non-finite t_start");
     if (!dL_dwave || !workspace || !dL_dphi0 || !dL_dpi0) return fail(c, TEUK_EINVAL, "NULL buffer");

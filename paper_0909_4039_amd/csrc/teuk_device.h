@@ -189,6 +189,48 @@ __device__ __forceinline__ Rad<R> lds_rad(const R (*t)[WAVE], int lane) {
     return r;
 }
 
+// The forward step keeps the radial numerators R_W2 .. R_VI in LDS and the
+// source's radial factor separately, per fused step and location, so that
+// a moving source can be evaluated at each stage's time.
+constexpr int N_RAD_FWD = 8;
+static_assert(R_VI == N_RAD_FWD - 1, "forward LDS radial fields are the first table fields");
+
+template <typename R>
+__device__ __forceinline__ Rad<R> lds_rad_fwd(const R (*t)[WAVE], int lane) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    lane += z;
+    Rad<R> r;
+    r.w2 = t[0][lane];
+    r.del = t[1][lane];
+    r.wbn = t[2][lane];
+    r.ctr = t[3][lane];
+    r.cti0 = t[4][lane];
+    r.crr = t[5][lane];
+    r.vr = t[6][lane];
+    r.vi = t[7][lane];
+    r.gr = R(0);   // the forward step reads the source factor from its own slots
+    return r;
+}
+
+// One LDS value of this lane through a hidden index (see lds_rad).
+template <typename R>
+__device__ __forceinline__ R lds_lane(const R* t, int lane) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return t[lane + z];
+}
+
+// Per-wave LDS of the forward step: radial numerators at half and integer
+// points, and the source's radial factor per fused step k at the
+// predictor's (half point, t^{n+k}) and the corrector's (integer point,
+// t^{n+k} + dt/2) location and time.
+template <typename R, int KB>
+struct FwdLds {
+    R rad[2][N_RAD_FWD][WAVE];
+    R src[KB][2][WAVE];
+};
+
 // Angular factors of one theta row (wave-uniform: scalar loads).
 template <typename R>
 struct Ang {

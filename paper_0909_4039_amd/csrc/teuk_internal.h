@@ -107,6 +107,12 @@ struct StepArgs {
     int64_t wave_row[KB_MAX];
     int32_t iobs;
     R alpha;
+    // moving source: centre r*0 at the predictor (2k) and corrector (2k+1)
+    // times of fused step k; the radial factor is exp(-(r* - r*0)^2 / two_sr2)
+    int32_t moving;
+    R rs0[2 * KB_MAX];
+    R two_sr2;
+    R rmin, dr;
 };
 
 // Arguments of one launch of the reverse sweep (FP64 only).  Stage k of a

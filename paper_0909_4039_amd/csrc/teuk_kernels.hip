@@ -54,8 +54,8 @@ struct Stage {
 };
 
 template <typename R>
-__device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2ma_idr, R idr, R tau, cx<R> ph,
-                                          cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df, cx<R> dg) {
+__device__ __forceinline__ Stage<R> stage(const Rad<R>& q, R gr, const Ang<R>& g, R m2ma_idr, R idr, R tau,
+                                          cx<R> ph, cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df, cx<R> dg) {
     R S2 = fma(q.w2, q.w2, -g.a2s2 * q.del);   // Sigma^2
     R y = rsqrt_full(S2);                      // 1/Sigma
     R y2 = y * y;
@@ -65,7 +65,7 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, const Ang<R>& g, R m2
     cx<R> CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
     cx<R> V = {q.vr, q.vi};
     cx<R> acc = cfma(CR, df, cfma(V, f, cmul(CT, X)));
-    cx<R> T = (g.agth * q.gr) * ph;
+    cx<R> T = (g.agth * gr) * ph;   // source: amp x theta Gaussian x radial factor x phase
     Stage<R> o;
     o.phi = {fma(tau, X.re, f0.re), fma(tau, X.im, f0.im)};
     cx<R> rhs = {fma(bi, dg.re, fma(-y2, acc.re, T.re)), fma(bi, dg.im, fma(-y2, acc.im, T.im))};
@@ -113,7 +113,8 @@ __device__ __forceinline__ void pipe_init(Pipe<R>& st, int olo, int ohi, int nth
 template <typename R>
 struct Consts {
     const R* ang;
-    const R (*srad)[N_RAD_USED][WAVE];
+    const R (*srad)[N_RAD_FWD][WAVE];
+    const R (*ssrc)[2][WAVE];   // source radial factor [fused step][half/integer][lane]
     int lane, nth;
     R keep, idr, dt, hdt, m2ma_idr;
 };
@@ -123,7 +124,7 @@ struct Consts {
 // L-2 (okQ).  The parts of the iteration sit behind wave-uniform branches,
 // which also keep the scheduler from stretching live ranges.
 template <typename R>
-__device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L, cx<R> p, cx<R> q,
+__device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int ks, int L, cx<R> p, cx<R> q,
                                           cx<R> ph0, cx<R> ph1, R* wave, int64_t wrow, int wl, int rlo,
                                           int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
     const R half = R(0.5);
@@ -162,8 +163,9 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     //      bracket of its stencil
     if (L >= st.plo && L <= st.phi) {
         const Ang<R> g = load_ang(K.ang, L);
-        const Rad<R> qh = lds_rad<R>(K.srad[0], K.lane);   // half point c+1/2
-        Stage<R> o = stage(qh, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
+        const Rad<R> qh = lds_rad_fwd<R>(K.srad[0], K.lane);   // half point c+1/2
+        const R gr = lds_lane(K.ssrc[ks][0], K.lane);
+        Stage<R> o = stage(qh, gr, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
         st.hP = o.phi;
         st.hQp = o.pi_part;
         st.hD = o.dw;
@@ -182,8 +184,9 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int L
     okP = (P >= st.olo && P < st.ohi);
     if (okP) {
         const Ang<R> g = load_ang(K.ang, P);
-        const Rad<R> qi = lds_rad<R>(K.srad[1], K.lane);   // integer point c
-        Stage<R> o = stage(qi, g, K.m2ma_idr, K.idr, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
+        const Rad<R> qi = lds_rad_fwd<R>(K.srad[1], K.lane);   // integer point c
+        const R gr = lds_lane(K.ssrc[ks][1], K.lane);
+        Stage<R> o = stage(qi, gr, g, K.m2ma_idr, K.idr, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
         st.nQp = o.pi_part;
         st.nD = o.dw;
         outP = K.keep * o.phi;
@@ -207,7 +210,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
                                           R* __restrict__ phi_out, R* __restrict__ pi_out,
                                           const R* __restrict__ rad_i, const R* __restrict__ rad_h,
                                           const R* __restrict__ ang, R* __restrict__ wave, const P& A,
-                                          int strip, int chunk, R (*srad)[N_RAD_USED][WAVE]) {
+                                          int strip, int chunk, FwdLds<R, KB>* lds) {
     constexpr int SO = WAVE - 2 * KB;   // valid output columns per strip
     const int lane = threadIdx.x & (WAVE - 1);
     const int nr = A.nr(), nth = A.nth();
@@ -219,11 +222,27 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     // radial numerators of this wavefront's columns (CRR and WBN, which
     // multiply r* differences only, carry the 1/dr* of those differences)
     const R idr = A.inv_dr();
-    for (int k = 0; k < 2 * N_RAD_USED; ++k) {
-        const int loc = k / N_RAD_USED, f = k % N_RAD_USED;
+    R (*srad)[N_RAD_FWD][WAVE] = lds->rad;
+    for (int k = 0; k < 2 * N_RAD_FWD; ++k) {
+        const int loc = k / N_RAD_FWD, f = k % N_RAD_FWD;
         const R v = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
         srad[loc][f][lane] = (f == R_CRR || f == R_WBN) ? v * idr : v;
     }
+    // source radial factor of each fused step at its predictor (half point,
+    // t^{n+k}) and corrector (integer point, t^{n+k} + dt/2): the table's
+    // for a fixed orbit, exp(-(r* - r*0(t))^2 / (2 sr^2)) for a moving one
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        for (int loc = 0; loc < 2; ++loc) {
+            R v;
+            if (A.moving()) {
+                const R x = fma((R)c + (loc == 0 ? R(0.5) : R(0)), A.dr(), A.rmin()) - A.rs0(2 * k + loc);
+                v = exp((-x * x) / A.two_sr2());
+            } else {
+                v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * A.stride() + cu];
+            }
+            lds->src[k][loc][lane] = v;
+        }
     const int j0 = chunk * A.rows();
     const int jend = min(j0 + A.rows(), nth);
     const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
@@ -232,6 +251,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     Consts<R> K;
     K.ang = ang;
     K.srad = srad;
+    K.ssrc = lds->src;
     K.lane = lane;
     K.nth = nth;
     K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
@@ -274,8 +294,8 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
             cx<R> oP, oQ;
             bool okP, okQ;
             const cx<R> ph0 = A.ph(2 * k), ph1 = A.ph(2 * k + 1);
-            pipe_iter(st[k], K, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend, A.alpha(), oP,
-                      okP, oQ, okQ);
+            pipe_iter(st[k], K, k, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend, A.alpha(),
+                      oP, okP, oQ, okQ);
             if (k == KB - 1) {
                 if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, oQ);
                 if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, oP);
@@ -312,6 +332,11 @@ struct ArgParams {
     __device__ R alpha() const { return A.alpha; }
     __device__ cx<R> ph(int i) const { return {A.ph[i][0], A.ph[i][1]}; }
     __device__ int64_t wave_row(int k) const { return A.wave_row[k]; }
+    __device__ bool moving() const { return A.moving != 0; }
+    __device__ R rs0(int i) const { return A.rs0[i]; }
+    __device__ R two_sr2() const { return A.two_sr2; }
+    __device__ R rmin() const { return A.rmin; }
+    __device__ R dr() const { return A.dr; }
 };
 
 // Single-mode launch: one tile per wavefront, WG_WAVES adjacent strips of
@@ -341,9 +366,9 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     }
     const int strip = grp * WG_WAVES + wid;
     if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
-    __shared__ R srad_all[WG_WAVES][2][N_RAD_USED][WAVE];   // [wave][half/integer][field][lane]
+    __shared__ FwdLds<R, KB> lds_all[WG_WAVES];   // one slice per wavefront
     const ArgParams<R> P{A};
-    step_tile<R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, srad_all[wid]);
+    step_tile<R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, &lds_all[wid]);
 }
 
 template <typename R>
@@ -398,11 +423,17 @@ struct InstParams {
         const int64_t row = clk->step + step_off + q;
         return (record && I->wave != nullptr && row < I->wave_cap) ? row : -1;
     }
+    // batched instances have fixed orbits
+    __device__ bool moving() const { return false; }
+    __device__ double rs0(int) const { return 0.0; }
+    __device__ double two_sr2() const { return 1.0; }
+    __device__ double rmin() const { return 0.0; }
+    __device__ double dr() const { return 0.0; }
 };
 
 template <int KB>
 __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, const BatchArgs& B,
-                                           double (*srad)[N_RAD_USED][WAVE]) {
+                                           FwdLds<double, KB>* lds) {
     constexpr int SO = WAVE - 2 * KB;
     const InstParams P{I, clk, B.record, B.step_off};
     const int src = (int)((clk->launches + B.launch_off) & 1);
@@ -413,7 +444,7 @@ __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, 
     const int strip = (local - chunk * ngrp) * WG_WAVES + wid;
     if (strip < n_strips)
         step_tile<double, KB>(I->buf[src][0], I->buf[src][1], I->buf[1 - src][0], I->buf[1 - src][1], I->rad_i,
-                              I->rad_h, I->ang, I->wave, P, strip, chunk, srad);
+                              I->rad_h, I->ang, I->wave, P, strip, chunk, lds);
 }
 
 // Persistent form: the grid holds as many workgroups as stay resident and
@@ -422,7 +453,7 @@ __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, 
 template <int KB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_kernel(BatchArgs B) {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    __shared__ FwdLds<double, KB> lds_all[WG_WAVES];
     const cinst insts = (cinst)B.inst;
     const cclock clk = (cclock)B.clock;
     const int X = 8;
@@ -431,7 +462,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int i = 0;
     for (int t = t_lo + kx; t < t_hi; t += nbx) {
         while (i + 1 < B.n_inst && insts[i + 1].first_tile[KB - 1] <= t) ++i;
-        batch_tile<KB>(insts + i, clk, t, wid, B, srad_all[wid]);
+        batch_tile<KB>(insts + i, clk, t, wid, B, &lds_all[wid]);
     }
 }
 
@@ -440,7 +471,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 template <int KB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_grid_kernel(BatchArgs B) {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    __shared__ FwdLds<double, KB> lds_all[WG_WAVES];
     const cinst insts = (cinst)B.inst;
     const cclock clk = (cclock)B.clock;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -450,7 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         if (insts[mid].first_tile[KB - 1] <= t) lo = mid;
         else hi = mid - 1;
     }
-    batch_tile<KB>(insts + lo, clk, t, wid, B, srad_all[wid]);
+    batch_tile<KB>(insts + lo, clk, t, wid, B, &lds_all[wid]);
 }
 
 int batch_blocks_per_cu(int kb) {

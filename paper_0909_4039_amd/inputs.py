@@ -73,3 +73,36 @@ def smooth_random_state(nr, nth, rstar_min, rstar_max, seed, n_modes=4):
         phi += ph * Y[:, None] * g[None, :]
         pi += (rng.standard_normal() + 1j * rng.standard_normal()) * 0.3 * Y[:, None] * g[None, :]
     return phi, pi
+
+
+def isco_radius(a: float, M: float = 1.0) -> float:
+    """Prograde innermost stable circular orbit (Bardeen, Press & Teukolsky 1972)."""
+    x = a / M
+    z1 = 1.0 + (1.0 - x * x) ** (1.0 / 3.0) * ((1.0 + x) ** (1.0 / 3.0) + (1.0 - x) ** (1.0 / 3.0))
+    z2 = np.sqrt(3.0 * x * x + z1 * z1)
+    return float(M * (3.0 + z2 - np.sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2))))
+
+
+def inspiral_trajectory(r_start, a, M, q, dt, n_steps, substeps=8):
+    """Orbit of a slowly inspiralling particle, sampled at every half step.
+
+    Returns an array (2 n_steps + 1, 2): row k = (r0, phi) at t = k dt / 2.
+    r0(t) = (r_start^4 - (256/5) q M^3 t)^(1/4), the quadrupole
+    radiation-reaction decay of a circular orbit of mass ratio q (Peters
+    1964), held at the prograde ISCO once it gets there; phi(t) is the
+    integral of Omega(r0) = sqrt(M) / (r0^(3/2) + a sqrt(M)), by the
+    trapezoid rule on `substeps` points per half step.  q = 0 gives a fixed
+    orbit with phi = Omega t.
+    """
+    r_isco = isco_radius(a, M)
+    k = 256.0 / 5.0 * q * M ** 3
+    n_half = 2 * int(n_steps) + 1
+    t = np.arange((n_half - 1) * substeps + 1) * (0.5 * dt / substeps)
+    r = np.maximum((r_start ** 4 - k * t) ** 0.25 if k > 0 else np.full_like(t, float(r_start)), r_isco)
+    om = np.sqrt(M) / (r ** 1.5 + a * np.sqrt(M))
+    h = 0.5 * dt / substeps
+    phi = np.concatenate([[0.0], np.cumsum(0.5 * h * (om[1:] + om[:-1]))])
+    out = np.empty((n_half, 2))
+    out[:, 0] = r[::substeps]
+    out[:, 1] = phi[::substeps]
+    return out

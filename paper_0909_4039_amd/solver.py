@@ -80,6 +80,18 @@ class Solver:
         check(_lib.lib().teuk_set_source(self._ctx, r0, amp, sigma_r_cells, sigma_th_cells), self._ctx)
         self.source = (float(r0), float(amp), float(sigma_r_cells), float(sigma_th_cells))
 
+    def set_trajectory(self, r0_phase):
+        """Moving source: r0_phase[k] = (r0, phi) at t_now + k dt/2 (numpy (n, 2)); None: fixed orbit."""
+        if r0_phase is None:
+            check(_lib.lib().teuk_set_trajectory(self._ctx, None, 0), self._ctx)
+            return
+        import numpy as np
+        tab = np.ascontiguousarray(r0_phase, dtype=np.float64)
+        if tab.ndim != 2 or tab.shape[1] != 2:
+            raise ValueError("r0_phase must have shape (n, 2)")
+        check(_lib.lib().teuk_set_trajectory(self._ctx, tab.ctypes.data_as(ctypes.c_void_p), tab.shape[0]),
+              self._ctx)
+
     def set_observer(self, rstar_obs, capacity_rows):
         """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
         self.wave = torch.zeros((int(capacity_rows), self.shape[0]), dtype=self.dtype, device=self.device)
