@@ -59,6 +59,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-others", action="store_true")
+    p.add_argument("--no-copy", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
 
@@ -283,6 +284,66 @@ def time_small_and_mid():
     return out
 
 
+def copy_bandwidth(gib=2.0, reps=20):
+    """HBM bandwidth of a plain device-to-device copy (torch), read + write
+    bytes over time: the practical ceiling next to the 8 TB/s published peak."""
+    import torch
+    n = int(gib * 2 ** 30 / 16)
+    a = torch.empty(n, dtype=torch.complex128, device="cuda:0")
+    b = torch.empty_like(a)
+    a.zero_()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 16, "GBs": 2 * n * 16 / sec / 1e9}
+
+
+_CPU_SAMPLE = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle
+from paper_0909_4039_amd import workloads
+W = workloads.LARGE
+oracle.build()
+j0, nj = W.nth // 2 - 32, 64
+dt = oracle.stable_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+o = oracle.Oracle(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, r0=W.r0, amp=W.amp,
+                  rstar_obs=W.rstar_obs, window=(0, W.nr, j0, nj))
+phi = np.zeros((nj, W.nr), complex)
+pi = np.zeros((nj, W.nr), complex)
+t = time.perf_counter()
+phi, pi = o.step(phi, pi, 0.0)
+one = time.perf_counter() - t
+n = max(1, int({seconds} / max(one, 1e-6)) - 1)
+t = time.perf_counter()
+for k in range(n):
+    phi, pi = o.step(phi, pi, (k + 1) * dt)
+el = time.perf_counter() - t
+print(json.dumps({{"updates_per_s": W.nr * nj * n / el, "steps": n, "seconds": el, "threads": oracle.threads()}}))
+"""
+
+
+def cpu_baseline_single_thread(seconds):
+    """The same oracle sample on one thread, in a child process (OMP_NUM_THREADS=1)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _CPU_SAMPLE.format(root=ROOT, seconds=seconds)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(W, seconds):
     import numpy as np
     import oracle
@@ -314,10 +375,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU "
               "path", file=sys.stderr)
         sys.exit(2)
-    import torch
     from paper_0909_4039_amd import workloads
     W = workloads.LARGE
     pts = W.nr * W.nth
+    # the oracle's CPU baselines run first, before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(W, args.cpu_seconds)
+        cpu["single_thread"] = cpu_baseline_single_thread(args.cpu_seconds / 2)
+    import torch
     ms, dt, kb, tiling = time_solver(W, 64, args.steps, args.warmup)
     ms_step = ms / args.steps
     ups = pts * args.steps / (ms * 1e-3)
@@ -363,8 +429,12 @@ def main():
         out["batched"] = time_batched()
     if not args.no_others:
         out["other_workloads"] = time_small_and_mid()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+    if not args.no_copy:
+        cb = copy_bandwidth()
+        out["hbm_copy"] = dict(cb, note="torch device copy, 2 GiB read + 2 GiB write; context for the 8 TB/s peak",
+                               lw_step_per_launch_frac_of_copy=achieved / (cb["GBs"] * 1e9))
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -17,7 +17,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # no implicit multiply-add contraction: the kernels write each FMA out
     "-ffp-contract=off",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 

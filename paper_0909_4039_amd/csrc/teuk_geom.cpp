@@ -5,6 +5,8 @@
 // per context and uploaded.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <thread>
 
 #include "teuk_internal.h"
 
@@ -81,9 +83,28 @@ void build_geometry(Geometry& g) {
     g.stride = (g.nr + 63) / 64 * 64;
     g.rad_i.assign((size_t)R_NFIELDS * g.stride, 0.0);
     g.rad_h.assign((size_t)R_NFIELDS * g.stride, 0.0);
-    for (int64_t i = 0; i < g.nr; ++i) {
-        radial_entry(g, g.rmin + double(i) * g.dr, g.rad_i, i);
-        radial_entry(g, g.rmin + (double(i) + 0.5) * g.dr, g.rad_h, i);
+    // Each column inverts Eq. (2) on its own (a few microseconds): large
+    // grids split the columns over host threads (OMP_NUM_THREADS if set,
+    // else the hardware's count, at most 64).  Every entry is computed the
+    // same way whatever the split.
+    auto fill = [&g](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            radial_entry(g, g.rmin + double(i) * g.dr, g.rad_i, i);
+            radial_entry(g, g.rmin + (double(i) + 0.5) * g.dr, g.rad_h, i);
+        }
+    };
+    int64_t nt = 1;
+    if (g.nr >= 65536) {
+        const char* env = std::getenv("OMP_NUM_THREADS");
+        nt = env ? std::atoi(env) : (int64_t)std::thread::hardware_concurrency();
+        nt = std::min<int64_t>(std::max<int64_t>(nt, 1), 64);
+    }
+    if (nt == 1) {
+        fill(0, g.nr);
+    } else {
+        std::vector<std::thread> pool;
+        for (int64_t t = 0; t < nt; ++t) pool.emplace_back(fill, g.nr * t / nt, g.nr * (t + 1) / nt);
+        for (std::thread& th : pool) th.join();
     }
     // padding columns repeat the last node so that clamped reads stay finite
     for (int f = 0; f < R_NFIELDS; ++f)
