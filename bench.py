@@ -344,6 +344,40 @@ def cpu_baseline_single_thread(seconds):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def fp32_error():
+    """FP32 against FP64 on the GPU path (FP64 matches the oracle to 1e-12):
+    relative L2 error of the extracted waveform for the Schwarzschild pulse
+    (256 x 64, 2000 steps, read at r* = 30 where the pulse arrives) and for
+    the Kerr a = 0.9 source grid (8192 x 256, smooth seeded data, 2000
+    steps, read at r* = 20)."""
+    import numpy as np
+    import torch
+    from paper_0909_4039_amd import inputs, workloads
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    out = {}
+    for W, n, robs in ((workloads.SCHWARZSCHILD_PULSE, 2000, 30.0), (workloads.KERR_SOURCE, 2000, 20.0)):
+        dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+        if W.pulse:
+            phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
+                                   inputs.seeded_amplitude(W.pulse["seed"]))
+        else:
+            phi, pi = inputs.smooth_random_state(W.nr, W.nth, W.rstar_min, W.rstar_max, seed=5)
+        waves = {}
+        for prec in (64, 32):
+            s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
+            if W.amp:
+                s.set_source(W.r0, W.amp)
+            s.set_state(phi, pi)
+            s.set_observer(robs, n + 1)
+            s.step(n)
+            torch.cuda.synchronize()
+            waves[prec] = s.wave.cpu().numpy().astype(np.complex128)
+            s.close()
+        err = float(np.linalg.norm(waves[32] - waves[64]) / np.linalg.norm(waves[64]))
+        out[W.name] = {"steps": n, "rstar_obs": robs, "waveform_rel_err": err, "bound": 1e-5}
+    return out
+
+
 def cpu_baseline(W, seconds):
     import numpy as np
     import oracle
@@ -422,7 +456,8 @@ def main():
                        "steps_per_launch": kb32,
                        "hbm_frac_per_launch": BYTES_PER_UPDATE[32] * pts / l32 / HBM_PEAK,
                        "effective_frac": BYTES_PER_UPDATE[32] * ups32 / HBM_PEAK,
-                       "traffic": measured_traffic(32)}
+                       "traffic": measured_traffic(32),
+                       "error_vs_fp64": fp32_error()}
     if not args.no_adjoint:
         out["adjoint"] = time_adjoint()
     if not args.no_batched:

@@ -282,3 +282,19 @@ def test_autotune_keeps_state_and_results(oracle_mod):
     for x, y in zip(got, ref):
         assert np.array_equal(x, y)
     s.close()
+
+
+def test_fp32_waveform_error_kerr_8192x256(oracle_mod):
+    # FP32 storage and arithmetic on the full Kerr a = 0.9 source grid against
+    # the FP64 oracle: smooth seeded data, 300 steps, waveform at r* = 20
+    nr, nth, rmin, rmax, a, m = 8192, 256, -100.0, 400.0, 0.9, 2
+    case = dict(name="c2_fp32", nr=nr, nth=nth, rmin=rmin, rmax=rmax, a=a, m=m, s=-2, robs=20.0, r0=10.0, amp=1.0)
+    case["dt"] = _dt(oracle_mod, case, 50000)
+    n = 300
+    phi, pi = inputs.smooth_random_state(nr, nth, rmin, rmax, seed=23)
+    print(f"[gpu] fp32 8192x256 n={n}", flush=True)
+    gp, gq, gw = run_gpu(case, phi, pi, n, prec=32)
+    op, oq, ow = run_oracle(oracle_mod, case, phi, pi, n)
+    err_w = rel(gw, ow)
+    print(f"[gpu] fp32 8192x256 waveform rel err {err_w:.3e}, state {rel(gp, op):.3e}", flush=True)
+    assert err_w <= 1e-5, err_w
