@@ -63,3 +63,32 @@ def test_gpu_ringdown_frequency(oracle_mod, gold):
     print(f"[gpu] a={a}: 1025 -> {w1:.5f}, 2049 -> {w2:.5f}, extrapolated {wx:.5f}, reference {ref}", flush=True)
     assert abs(w2.real - ref.real) < 0.005 * ref.real and abs(w2.imag - ref.imag) < 0.03 * abs(ref.imag)
     assert abs(wx.real - ref.real) < 0.005 * ref.real and abs(wx.imag - ref.imag) < 0.01 * abs(ref.imag)
+
+
+@pytest.mark.parametrize("m,s", [(2, -2), (3, -1)])
+def test_gpu_a0_evolution_stays_separable(oracle_mod, m, s):
+    # a = 0: data along a discrete angular eigenvector stays Y(theta) R(r*, t)
+    # on the GPU path too (every coefficient but Lth is theta-independent)
+    import torch
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    nr, nth, rmin, rmax = 4096, 64, -50.0, 150.0
+    A = oracle_mod.angular_matrix(nth, m, s)      # input profile only
+    ev, V = np.linalg.eig(A)
+    k = np.argmax(ev.real)
+    Y = np.real(V[:, k])
+    Y /= Y[np.argmax(np.abs(Y))]
+    rs, _ = inputs.grid(nr, nth, rmin, rmax)
+    g = np.exp(-(rs - 10.0) ** 2 / 18.0) * (1.0 + 0.5j)
+    phi = (Y[:, None] * g[None, :]).astype(complex)
+    pi = (Y[:, None] * (-(rs - 10.0) / 9.0 * g)[None, :]).astype(complex)
+    dt = suggest_dt(nr, nth, rmin, rmax, 0.0, 1.0, m, s, 3000)
+    sol = Solver(nr, nth, rmin, rmax, 0.0, 1.0, m, s, dt)
+    sol.set_state(phi, pi)
+    sol.step(3000)
+    torch.cuda.synchronize()
+    for f in (sol.phi.cpu().numpy(), sol.pi.cpu().numpy()):
+        R = f / Y[:, None]
+        spread = np.max(np.abs(R - R[nth // 2][None, :]))
+        print(f"[gpu] separability m={m} s={s}: spread {spread:.2e} of {np.max(np.abs(R)):.2e}", flush=True)
+        assert spread <= 1e-11 * np.max(np.abs(R))
+    sol.close()

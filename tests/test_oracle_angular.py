@@ -70,3 +70,27 @@ def test_ghost_sign_rule(oracle_mod):
         fp, fm = 1.0, sig
         want = (fp - 2 + fm) / dth ** 2 + np.cos(th0) / np.sin(th0) * (fp - fm) / (2 * dth) + P
         assert out[0].real == pytest.approx(want, rel=1e-13)
+
+
+@pytest.mark.parametrize("m,s", [(2, -2), (1, -2), (3, -1), (0, 2)])
+def test_a0_evolution_stays_separable(oracle_mod, m, s):
+    # a = 0: every coefficient but Lth is independent of theta, so data along a
+    # discrete angular eigenvector Y stays Y(theta) R(r*, t) for all time: the
+    # ratio Phi / Y must be the same in every row (to rounding).
+    nr, nth, rmin, rmax = 90, 20, -30.0, 60.0
+    A = oracle_mod.angular_matrix(nth, m, s)
+    ev, V = np.linalg.eig(A)
+    k = np.argmax(ev.real)                   # the least negative eigenvalue (lowest l)
+    Y = np.real(V[:, k])
+    Y /= Y[np.argmax(np.abs(Y))]
+    rs = rmin + np.arange(nr) * (rmax - rmin) / (nr - 1)
+    g = np.exp(-(rs - 10.0) ** 2 / 18.0) * (1.0 + 0.5j)
+    phi = (Y[:, None] * g[None, :]).astype(complex)
+    pi = (Y[:, None] * (-(rs - 10.0) / 9.0 * g)[None, :]).astype(complex)
+    dt = oracle_mod.stable_dt(nr, nth, rmin, rmax, 0.0, 1.0, m, s, 2000)
+    o = oracle_mod.Oracle(nr, nth, rmin, rmax, 0.0, 1.0, m, s, dt)
+    p, q, _ = o.run(phi, pi, 300, record=False)
+    for f in (p, q):
+        R = f / Y[:, None]                     # every row should give the same R(r*)
+        spread = np.max(np.abs(R - R[nth // 2][None, :]))
+        assert spread <= 1e-12 * np.max(np.abs(R)), spread
