@@ -12,7 +12,7 @@
 // K^H needs no forward state, so the sweep runs backwards from the loss
 // alone: no stored or recomputed forward steps.
 //
-// adj_step_kernel applies KB reverse steps per launch with the same tiling
+// adj_step_kernel1/2 apply KB = 1 or 2 reverse steps per launch with the same tiling
 // as the forward kernel: a wavefront owns a strip of 64 r* columns and
 // marches up through a chunk of theta rows.  The reverse step has the
 // forward step's footprint (r* +-1, theta +-2), with the lane shifts
@@ -221,11 +221,10 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
 }
 
 template <int KB>
-__global__ __launch_bounds__(256) void adj_step_kernel(const double* __restrict__ lp, const double* __restrict__ lq,
-                                                     double* __restrict__ lp_out, double* __restrict__ lq_out,
-                                                     const double* __restrict__ rad_i,
-                                                     const double* __restrict__ rad_h,
-                                                     const double* __restrict__ ang, AdjArgs A) {
+__device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, const double* __restrict__ lq,
+                                              double* __restrict__ lp_out, double* __restrict__ lq_out,
+                                              const double* __restrict__ rad_i, const double* __restrict__ rad_h,
+                                              const double* __restrict__ ang, const AdjArgs& A) {
     constexpr int SO = WAVE - 2 * KB;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -337,13 +336,29 @@ __global__ __launch_bounds__(256) void adj_step_kernel(const double* __restrict_
     }
 }
 
+// One reverse step per launch fits 4 waves per SIMD (128 VGPRs, no spills);
+// two fused steps need more registers and run at 2.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void adj_step_kernel1(
+    const double* __restrict__ lp, const double* __restrict__ lq, double* __restrict__ lp_out,
+    double* __restrict__ lq_out, const double* __restrict__ rad_i, const double* __restrict__ rad_h,
+    const double* __restrict__ ang, AdjArgs A) {
+    adj_step_body<1>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+}
+__global__ __launch_bounds__(256) void adj_step_kernel2(const double* __restrict__ lp, const double* __restrict__ lq,
+                                                       double* __restrict__ lp_out, double* __restrict__ lq_out,
+                                                       const double* __restrict__ rad_i,
+                                                       const double* __restrict__ rad_h,
+                                                       const double* __restrict__ ang, AdjArgs A) {
+    adj_step_body<2>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+}
+
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s) {
     int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
     if (a.kb == 2)
-        hipLaunchKernelGGL(adj_step_kernel<2>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
+        hipLaunchKernelGGL(adj_step_kernel2, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
                            a.lq_out, a.rad_i, a.rad_h, a.ang, a);
     else
-        hipLaunchKernelGGL(adj_step_kernel<1>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
+        hipLaunchKernelGGL(adj_step_kernel1, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
                            a.lq_out, a.rad_i, a.rad_h, a.ang, a);
 }
 
