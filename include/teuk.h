@@ -42,7 +42,8 @@ extern "C" {
 #define TEUK_OK 0
 #define TEUK_EINVAL (-1)    /* an argument is out of range                     */
 #define TEUK_ESTATE (-2)    /* call out of order (e.g. no state bound)         */
-#define TEUK_EDEVICE (-3)   /* a HIP call failed; teuk_last_error has the text */
+#define TEUK_EDEVICE (-3)   /* a HIP call or a host allocation failed; teuk_last_error has the text.
+                               No C++ exception leaves any entry point. */
 #define TEUK_EUNSTABLE (-4) /* non-finite values found in the state            */
 #define TEUK_ENOTSUP (-5)   /* valid request this build does not serve         */
 

@@ -318,16 +318,8 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
 
 extern "C" {
 
-int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, double dt, int32_t prec,
-                void* hip_stream, teuk_ctx** out) {
-    if (!out) return TEUK_EINVAL;
-    *out = nullptr;
-    if (validate_phys(g, a, M, s) != TEUK_OK) return TEUK_EINVAL;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return TEUK_EINVAL;
-    if (prec != TEUK_FP64 && prec != TEUK_FP32) return TEUK_EINVAL;
-    if (m < -1000 || m > 1000) return TEUK_EINVAL;
-    teuk_ctx* c = new (std::nothrow) teuk_ctx();
-    if (!c) return TEUK_EDEVICE;
+static int init_ctx(teuk_ctx* c, const teuk_grid* g, double a, double M, int32_t m, int32_t s, double dt,
+                    int32_t prec, void* hip_stream) {
     c->prec = prec;
     c->dt = dt;
     c->stream = (hipStream_t)hip_stream;
@@ -347,13 +339,31 @@ int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, do
         hipMalloc(&c->d_rad_i, geo.rad_i.size() * es) != hipSuccess ||
         hipMalloc(&c->d_rad_h, geo.rad_h.size() * es) != hipSuccess ||
         hipMalloc(&c->d_ang, geo.ang.size() * es) != hipSuccess ||
-        hipMalloc((void**)&c->d_flag, sizeof(unsigned int)) != hipSuccess) {
-        teuk_destroy(c);
+        hipMalloc((void**)&c->d_flag, sizeof(unsigned int)) != hipSuccess)
         return TEUK_EDEVICE;
+    if (upload_tables(c) != TEUK_OK) return TEUK_EDEVICE;
+    return TEUK_OK;
+}
+
+int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, double dt, int32_t prec,
+                void* hip_stream, teuk_ctx** out) {
+    if (!out) return TEUK_EINVAL;
+    *out = nullptr;
+    if (validate_phys(g, a, M, s) != TEUK_OK) return TEUK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return TEUK_EINVAL;
+    if (prec != TEUK_FP64 && prec != TEUK_FP32) return TEUK_EINVAL;
+    if (m < -1000 || m > 1000) return TEUK_EINVAL;
+    teuk_ctx* c = new (std::nothrow) teuk_ctx();
+    if (!c) return TEUK_EDEVICE;
+    int rc;
+    try {
+        rc = init_ctx(c, g, a, M, m, s, dt, prec, hip_stream);
+    } catch (...) {  // host allocation or thread start failed; no C++ exception crosses the ABI
+        rc = TEUK_EDEVICE;
     }
-    if (upload_tables(c) != TEUK_OK) {
+    if (rc != TEUK_OK) {
         teuk_destroy(c);
-        return TEUK_EDEVICE;
+        return rc;
     }
     *out = c;
     return TEUK_OK;
@@ -388,7 +398,7 @@ int teuk_bind_state(teuk_ctx* c, void* phi, void* pi, void* phi_next, void* pi_n
     return TEUK_OK;
 }
 
-int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, double sigma_th_cells) {
+static int teuk_set_source_impl(teuk_ctx* c, double r0, double amp, double sigma_r_cells, double sigma_th_cells) {
     if (!c) return TEUK_EINVAL;
     Geometry& g = c->geo;
     if (!std::isfinite(amp) || !std::isfinite(r0)) return fail(c, TEUK_EINVAL, "non-finite source parameter");
@@ -405,7 +415,15 @@ int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, do
     return upload_tables(c);
 }
 
-int teuk_set_trajectory(teuk_ctx* c, const double* r0_phase, int64_t n_half) {
+int teuk_set_source(teuk_ctx* c, double r0, double amp, double sigma_r_cells, double sigma_th_cells) {
+    try {
+        return teuk_set_source_impl(c, r0, amp, sigma_r_cells, sigma_th_cells);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation or thread start failed");
+    }
+}
+
+static int teuk_set_trajectory_impl(teuk_ctx* c, const double* r0_phase, int64_t n_half) {
     if (!c) return TEUK_EINVAL;
     if (!r0_phase) {
         c->traj.clear();
@@ -421,6 +439,14 @@ int teuk_set_trajectory(teuk_ctx* c, const double* r0_phase, int64_t n_half) {
     c->traj_n = n_half;
     c->traj_step0 = c->step;
     return TEUK_OK;
+}
+
+int teuk_set_trajectory(teuk_ctx* c, const double* r0_phase, int64_t n_half) {
+    try {
+        return teuk_set_trajectory_impl(c, r0_phase, n_half);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation or thread start failed");
+    }
 }
 
 int teuk_set_observer(teuk_ctx* c, double rstar_obs, void* wave, int64_t capacity_rows) {
@@ -444,7 +470,7 @@ int teuk_set_observer(teuk_ctx* c, double rstar_obs, void* wave, int64_t capacit
     return TEUK_OK;
 }
 
-int teuk_step(teuk_ctx* c, int64_t n) {
+static int teuk_step_impl(teuk_ctx* c, int64_t n) {
     if (!c) return TEUK_EINVAL;
     if (c->status != TEUK_OK) return c->status;
     if (n < 0) return fail(c, TEUK_EINVAL, "negative step count");
@@ -460,6 +486,14 @@ int teuk_step(teuk_ctx* c, int64_t n) {
     }
     if (c->prec == 64) return launch_steps<double>(c, n);
     return launch_steps<float>(c, n);
+}
+
+int teuk_step(teuk_ctx* c, int64_t n) {
+    try {
+        return teuk_step_impl(c, n);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation or thread start failed");
+    }
 }
 
 int teuk_extract(teuk_ctx* c, double rstar_obs, void* out) {
@@ -527,7 +561,7 @@ int teuk_set_blocking(teuk_ctx* c, int32_t steps_per_launch) {
 
 int teuk_get_blocking(teuk_ctx* c) { return c ? c->kblock : TEUK_EINVAL; }
 
-int teuk_autotune(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out) {
+static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out) {
     if (!c) return TEUK_EINVAL;
     if (c->status != TEUK_OK) return c->status;
     if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
@@ -573,6 +607,14 @@ int teuk_autotune(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, in
     return TEUK_OK;
 }
 
+int teuk_autotune(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out) {
+    try {
+        return teuk_autotune_impl(c, launches_per_trial, rows_out, kb_out);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation or thread start failed");
+    }
+}
+
 int teuk_get_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* order) {
     if (!c) return TEUK_EINVAL;
     if (rows_per_wave) *rows_per_wave = c->rows;
@@ -586,7 +628,7 @@ int64_t teuk_adjoint_workspace_bytes(teuk_ctx* c) {
     return adjoint_layout(c).total;
 }
 
-int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+static int teuk_adjoint_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
                  void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
                  double* dL_damp) {
     if (!c) return TEUK_EINVAL;
@@ -637,6 +679,16 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
     return TEUK_OK;
 }
 
+int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+                 void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
+                 double* dL_damp) {
+    try {
+        return teuk_adjoint_impl(c, rstar_obs, dL_dwave, n_steps, t_start, workspace, workspace_bytes, dL_dphi0, dL_dpi0, dL_dr0, dL_damp);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation or thread start failed");
+    }
+}
+
 int teuk_check_finite(teuk_ctx* c) {
     if (!c) return TEUK_EINVAL;
     if (c->status != TEUK_OK) return c->status;
@@ -671,7 +723,7 @@ const char* teuk_strerror(int code) {
     }
 }
 
-int teuk_suggest_dt(const teuk_grid* g, double a, double M, int32_t m, int32_t s, int64_t n_steps, double* dt_out) {
+static int teuk_suggest_dt_impl(const teuk_grid* g, double a, double M, int32_t m, int32_t s, int64_t n_steps, double* dt_out) {
     if (!dt_out || n_steps < 1) return TEUK_EINVAL;
     if (validate_phys(g, a, M, s) != TEUK_OK) return TEUK_EINVAL;
     Geometry geo;
@@ -689,6 +741,14 @@ int teuk_suggest_dt(const teuk_grid* g, double a, double M, int32_t m, int32_t s
     if (wmax > 0.0) dt = std::min(dt, std::pow(8.0 / double(n_steps), 0.25) / wmax);
     *dt_out = dt;
     return TEUK_OK;
+}
+
+int teuk_suggest_dt(const teuk_grid* g, double a, double M, int32_t m, int32_t s, int64_t n_steps, double* dt_out) {
+    try {
+        return teuk_suggest_dt_impl(g, a, M, m, s, n_steps, dt_out);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return TEUK_EDEVICE;
+    }
 }
 
 double teuk_rstar_of_r(double r, double a, double M) {

@@ -58,6 +58,7 @@ int bfail(teuk_batch* b, int code, const char* fmt, ...) {
     } while (0)
 
 int dev_copy(teuk_batch* b, void** dst, const void* src, size_t bytes) {
+    b->allocs.reserve(b->allocs.size() + 1);  // a failed push_back must not lose the device block
     BHIP(b, hipMalloc(dst, bytes));
     b->allocs.push_back(*dst);
     BHIP(b, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -147,18 +148,7 @@ int ready(teuk_batch* b) {
 
 extern "C" {
 
-int teuk_batch_create(int32_t n, const teuk_desc* d, int64_t max_steps, void* hip_stream, teuk_batch** out) {
-    if (!out) return TEUK_EINVAL;
-    *out = nullptr;
-    if (n < 1 || n > 65535 || !d || max_steps < 1 || max_steps > ((int64_t)1 << 40)) return TEUK_EINVAL;
-    for (int i = 0; i < n; ++i) {
-        const teuk_desc& e = d[i];
-        if (validate_phys(&e.grid, e.a, e.M, e.s) != TEUK_OK) return TEUK_EINVAL;
-        if (!(e.dt > 0.0) || !std::isfinite(e.dt) || e.m < -1000 || e.m > 1000) return TEUK_EINVAL;
-        if (!std::isfinite(e.r0) || !std::isfinite(e.amp) || !std::isfinite(e.rstar_obs)) return TEUK_EINVAL;
-    }
-    teuk_batch* b = new (std::nothrow) teuk_batch();
-    if (!b) return TEUK_EDEVICE;
+static int init_batch(teuk_batch* b, int32_t n, const teuk_desc* d, int64_t max_steps, void* hip_stream) {
     b->n = n;
     b->stream = (hipStream_t)hip_stream;
     b->max_steps = max_steps;
@@ -168,10 +158,8 @@ int teuk_batch_create(int32_t n, const teuk_desc* d, int64_t max_steps, void* hi
     int rc = TEUK_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        teuk_batch_destroy(b);
+        hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return TEUK_EDEVICE;
-    }
     for (int kb = 1; kb <= KB_MAX; ++kb) b->per_cu[kb - 1] = batch_blocks_per_cu(kb);
     for (int i = 0; i < n && rc == TEUK_OK; ++i) {
         const teuk_desc& e = d[i];
@@ -246,6 +234,27 @@ int teuk_batch_create(int32_t n, const teuk_desc* d, int64_t max_steps, void* hi
     if (rc == TEUK_OK) {
         BatchClock z{0, 0};
         if (hipMemcpy(b->d_clock, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) rc = TEUK_EDEVICE;
+    }
+    return rc;
+}
+
+int teuk_batch_create(int32_t n, const teuk_desc* d, int64_t max_steps, void* hip_stream, teuk_batch** out) {
+    if (!out) return TEUK_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 65535 || !d || max_steps < 1 || max_steps > ((int64_t)1 << 40)) return TEUK_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const teuk_desc& e = d[i];
+        if (validate_phys(&e.grid, e.a, e.M, e.s) != TEUK_OK) return TEUK_EINVAL;
+        if (!(e.dt > 0.0) || !std::isfinite(e.dt) || e.m < -1000 || e.m > 1000) return TEUK_EINVAL;
+        if (!std::isfinite(e.r0) || !std::isfinite(e.amp) || !std::isfinite(e.rstar_obs)) return TEUK_EINVAL;
+    }
+    teuk_batch* b = new (std::nothrow) teuk_batch();
+    if (!b) return TEUK_EDEVICE;
+    int rc;
+    try {
+        rc = init_batch(b, n, d, max_steps, hip_stream);
+    } catch (...) {  // host allocation failed; no C++ exception crosses the ABI
+        rc = TEUK_EDEVICE;
     }
     if (rc != TEUK_OK) {
         teuk_batch_destroy(b);
