@@ -35,7 +35,10 @@ class TeukWaveform(torch.autograd.Function):
         solver.set_time(float(t_start), 0)
         wave = solver.set_observer(rstar_obs, int(n_steps) + 1)
         solver.step(int(n_steps))
+        cur = torch.cuda.current_stream(solver.device)
+        cur.wait_stream(solver.stream)   # the steps ran on the solver's stream
         out = wave.clone()
+        wave.record_stream(cur)
         solver.clear_observer()
         ctx.solver = solver
         ctx.args = (r0f, ampf, sig, int(n_steps), float(rstar_obs), float(t_start))

@@ -63,12 +63,17 @@ class Batch:
         return _check(_lib.lib().teuk_batch_current(self._b), self._b)
 
     def phi(self, i):
+        """Instance i's latest Phi; the batch writes it on its own stream, so
+        call ``synchronize`` before reading it on another."""
         return self._bufs[i][2 * self._cur()]
 
     def pi(self, i):
         return self._bufs[i][2 * self._cur() + 1]
 
     def set_state(self, i, phi, pi):
+        """Copy (phi, pi) into instance i's current pair on the batch's stream,
+        ordered after work already queued on the caller's current stream."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.stream):
             self.phi(i).copy_(torch.as_tensor(phi).to(self.device, torch.complex128))
             self.pi(i).copy_(torch.as_tensor(pi).to(self.device, torch.complex128))

@@ -47,7 +47,8 @@ class Solver:
         self.params = dict(nr=nr, nth=nth, rstar_min=rstar_min, rstar_max=rstar_max, a=a, M=M, m=m, s=s, dt=dt)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            self._bufs = [torch.zeros(self.shape, dtype=self.dtype, device=self.device) for _ in range(4)]
+            with torch.cuda.stream(self.stream):  # zero fill ordered before the library's launches
+                self._bufs = [torch.zeros(self.shape, dtype=self.dtype, device=self.device) for _ in range(4)]
             g = TeukGrid(nr, nth, rstar_min, rstar_max)
             ctx = ctypes.c_void_p()
             check(_lib.lib().teuk_create(ctypes.byref(g), a, M, m, s, dt, self.prec,
@@ -70,7 +71,9 @@ class Solver:
         return self._bufs[2 * self._cur() + 1]
 
     def set_state(self, phi, pi):
-        """Copy (phi, pi) into the current state buffers (on the solver's stream)."""
+        """Copy (phi, pi) into the current state buffers (on the solver's stream,
+        ordered after work already queued on the caller's current stream)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.stream):
             self.phi.copy_(torch.as_tensor(phi).to(self.device, self.dtype))
             self.pi.copy_(torch.as_tensor(pi).to(self.device, self.dtype))
@@ -94,7 +97,8 @@ class Solver:
 
     def set_observer(self, rstar_obs, capacity_rows):
         """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
-        self.wave = torch.zeros((int(capacity_rows), self.shape[0]), dtype=self.dtype, device=self.device)
+        with torch.cuda.stream(self.stream):
+            self.wave = torch.zeros((int(capacity_rows), self.shape[0]), dtype=self.dtype, device=self.device)
         check(_lib.lib().teuk_set_observer(self._ctx, rstar_obs, self.wave.data_ptr(), int(capacity_rows)),
               self._ctx)
         return self.wave
@@ -107,7 +111,8 @@ class Solver:
         check(_lib.lib().teuk_step(self._ctx, int(n)), self._ctx)
 
     def extract(self, rstar_obs):
-        out = torch.empty((self.shape[0],), dtype=self.dtype, device=self.device)
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((self.shape[0],), dtype=self.dtype, device=self.device)
         check(_lib.lib().teuk_extract(self._ctx, rstar_obs, out.data_ptr()), self._ctx)
         return out
 
