@@ -107,6 +107,7 @@ def time_adjoint(steps=None):
 
     s.set_state(phi, pi)
     tuned = s.autotune(10)
+    adj_tuned = s.adjoint_autotune(10)
 
     def forward():
         s.set_state(phi, pi)
@@ -131,7 +132,8 @@ def time_adjoint(steps=None):
     s.close()
     return {"workload": W.name, "steps": n, "forward_ms": fwd * 1e3, "adjoint_ms": min(adj) * 1e3,
             "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0,
-            "rows_per_wave": tuned[0], "steps_per_launch": tuned[1]}
+            "rows_per_wave": tuned[0], "steps_per_launch": tuned[1],
+            "adjoint_rows_per_wave": adj_tuned[0], "adjoint_steps_per_launch": adj_tuned[1]}
 
 
 def _pulse(w):

@@ -158,8 +158,9 @@ int teuk_get_blocking(teuk_ctx* ctx);
  *     aligned, caller-owned; contents are scratch.
  *   dL_dphi0, dL_dpi0: device, n_theta x n_rstar complex128 (written).
  *   dL_dr0, dL_damp: host, may be NULL; both 0 if no source was set.
- * Uses the context's dt, source, tiling and steps per launch, and neither
- * reads nor changes the bound state or the time.  Synchronous (returns
+ * Uses the context's dt, source and reverse-sweep tiling
+ * (teuk_set_adjoint_tiling), and neither reads nor changes the bound state
+ * or the time.  The workspace size does not depend on the tiling.  Synchronous (returns
  * after the sweep).  TEUK_ENOTSUP for FP32 contexts; TEUK_EINVAL for
  * misaligned, overlapping or short buffers or rstar_obs outside the grid. */
 int64_t teuk_adjoint_workspace_bytes(teuk_ctx* ctx);
@@ -176,8 +177,28 @@ int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t 
  * bitwise identical for every candidate, so tuning changes speed only.
  * Needs a bound state; the trial launches read the current pair and write
  * the other one, so the state, time and waveform are unchanged.  The
- * reverse sweep uses the same tiling. */
+ * reverse sweep has its own tiling (teuk_set_adjoint_tiling). */
 int teuk_autotune(teuk_ctx* ctx, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out);
+
+/* Tile shape of the reverse sweep (FP64; performance only: dL/du^0 is
+ * bitwise identical for every choice, the source gradients agree to
+ * rounding, since their partial sums follow the tiles).  rows_per_wave:
+ * theta rows per wavefront, 1..4096, or 0 (the default) to follow the step
+ * kernel's rows (teuk_set_tiling, teuk_autotune); steps_per_launch: 1 (the
+ * default) or 2 reverse steps per launch.  teuk_get_adjoint_tiling reports
+ * the rows in effect.  TEUK_EINVAL outside these ranges. */
+int teuk_set_adjoint_tiling(teuk_ctx* ctx, int32_t rows_per_wave, int32_t steps_per_launch);
+int teuk_get_adjoint_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* steps_per_launch);
+
+/* Autotuner of the reverse sweep (FP64, synchronous): as teuk_autotune over
+ * the same candidate rows times 1 or 2 reverse steps per launch, timing
+ * reverse-step launches that read the bound state's current pair as the
+ * adjoint and write the other pair, so the state, time and waveform are
+ * unchanged.  Allocates and frees a small device buffer for the trials'
+ * gradient partial sums.  Keeps the fastest as the reverse-sweep tiling and
+ * reports it (either pointer may be NULL).  TEUK_ENOTSUP for FP32 contexts,
+ * TEUK_ESTATE without a bound state. */
+int teuk_adjoint_autotune(teuk_ctx* ctx, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out);
 
 /* ------------------------------------------------------------- batches
  *

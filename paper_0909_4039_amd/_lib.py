@@ -55,6 +55,9 @@ _SIGS = {
     "teuk_adjoint": (ctypes.c_int, [_P, _D, _P, _I64, _D, _P, _I64, _P, _P, ctypes.POINTER(_D),
                                     ctypes.POINTER(_D)]),
     "teuk_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "teuk_set_adjoint_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "teuk_get_adjoint_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "teuk_adjoint_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_batch_create": (ctypes.c_int, [_I32, ctypes.POINTER(TeukDesc), _I64, _P, ctypes.POINTER(_P)]),
     "teuk_batch_destroy": (ctypes.c_int, [_P]),
     "teuk_batch_bind": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I64]),

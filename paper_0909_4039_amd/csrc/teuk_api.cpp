@@ -46,6 +46,9 @@ struct teuk_ctx {
     int order = 0;
     int kblock = 2;   // steps fused per launch
     bool rows_default = true;   // rows follow kblock until set explicitly
+    // tiling of the reverse sweep: adj_rows 0 follows the forward's rows
+    int adj_rows = 0;
+    int adj_kb = 1;
     // errors
     int status = TEUK_OK;
     char err[512] = {0};
@@ -211,18 +214,27 @@ int time_trial(teuk_ctx* c, int launches, double* sec_per_step) {
     return rc;
 }
 
-// Blocks of the reverse sweep's launch grid: the larger of the one- and
-// two-step grids at the current tiling.
-int64_t adjoint_blocks(const teuk_ctx* c) {
-    const Geometry& g = c->geo;
-    const int64_t nchunks = (g.nth + c->rows - 1) / c->rows;
+int adjoint_rows(const teuk_ctx* c) { return c->adj_rows > 0 ? c->adj_rows : c->rows; }
+
+// Blocks of the reverse sweep's launch grid at `rows` θ rows per wave and
+// kb steps per launch.
+int64_t adjoint_blocks(const Geometry& g, int rows, int kb) {
+    const int64_t nchunks = (g.nth + rows - 1) / rows;
+    const int64_t so = WAVE - 2 * kb;
+    const int64_t strips = (g.nr + so - 1) / so;
+    return (strips + WG_WAVES - 1) / WG_WAVES * nchunks;
+}
+
+// Gradient slots: one per wave of the launch grid.  The workspace holds
+// enough for any tiling (one row per wave, two steps per launch has the most
+// blocks), so its size does not change when the tiling does.
+int64_t adjoint_slots_max(const Geometry& g) {
     int64_t best = 0;
-    for (int kb = 1; kb <= KB_MAX; ++kb) {
-        const int64_t so = WAVE - 2 * kb;
-        const int64_t strips = (g.nr + so - 1) / so;
-        best = std::max(best, (strips + WG_WAVES - 1) / WG_WAVES * nchunks);
-    }
-    return best;
+    for (int kb = 1; kb <= KB_MAX; ++kb) best = std::max(best, adjoint_blocks(g, 1, kb));
+    return best * WG_WAVES;
+}
+int64_t adjoint_slots_used(const teuk_ctx* c) {
+    return adjoint_blocks(c->geo, adjoint_rows(c), c->adj_kb) * WG_WAVES;
 }
 
 int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -235,7 +247,7 @@ struct AdjLayout {
 AdjLayout adjoint_layout(const teuk_ctx* c) {
     AdjLayout L;
     const int64_t n = c->geo.nr * c->geo.nth;
-    L.n_slots = adjoint_blocks(c) * WG_WAVES;
+    L.n_slots = adjoint_slots_max(c->geo);
     L.lam = 0;
     L.slots = round256(2 * n * 16);
     L.result = L.slots + round256(L.n_slots * 3 * 8);
@@ -243,28 +255,11 @@ AdjLayout adjoint_layout(const teuk_ctx* c) {
     return L;
 }
 
-int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t n, double t_start, char* ws,
-                  double* dphi0, double* dpi0, double* res_host) {
+// Launch arguments of the reverse sweep that do not change from launch to
+// launch, at the context's reverse-sweep tiling.
+AdjArgs adjoint_args(const teuk_ctx* c, const double* g, int iobs, double alpha, double* slots) {
     const Geometry& geo = c->geo;
-    const AdjLayout lay = adjoint_layout(c);
-    const int64_t npts = geo.nr * geo.nth;
-    double* wl[2] = {(double*)(ws + lay.lam), (double*)(ws + lay.lam) + 2 * npts};
-    double* slots = (double*)(ws + lay.slots);
-    double* result = (double*)(ws + lay.result);
-    // launches from the top: kb steps each, the odd remainder last
-    std::vector<int> plan;
-    for (int64_t r = n; r > 0;) {
-        const int kb = (c->kblock >= 2 && r >= 2) ? 2 : 1;
-        plan.push_back(kb);
-        r -= kb;
-    }
-    // start in the pair that makes the last launch write (dphi0, dpi0)
-    double* pair[2][2] = {{dphi0, dpi0}, {wl[0], wl[1]}};
-    int cur = (plan.size() % 2 == 1) ? 1 : 0;
-    launch_adjoint_init(pair[cur][0], pair[cur][1], g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
-    HIP_TRY(c, hipGetLastError());
-    launch_fill_zero(slots, lay.n_slots * 3, c->stream);
-    HIP_TRY(c, hipGetLastError());
+    const int rows = adjoint_rows(c);
     AdjArgs a{};
     a.rad_i = (const double*)c->d_rad_i;
     a.rad_h = (const double*)c->d_rad_h;
@@ -272,8 +267,8 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
     a.stride = geo.stride;
     a.nr = (int)geo.nr;
     a.nth = (int)geo.nth;
-    a.rows = c->rows;
-    a.n_chunks = (int)((geo.nth + c->rows - 1) / c->rows);
+    a.rows = rows;
+    a.n_chunks = (int)((geo.nth + rows - 1) / rows);
     a.dt = c->dt;
     a.hdt = 0.5 * c->dt;
     a.inv_dr = 1.0 / geo.dr;
@@ -282,22 +277,57 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
     a.iobs = iobs;
     a.alpha = alpha;
     a.slots = slots;
+    return a;
+}
+
+// The per-launch part: kb reverse steps reading lambda^top, stage times and
+// source phases of the forward steps top-1 .. top-kb; the dL/dw rows are
+// injected when `inject` is set.
+void adjoint_launch_args(const teuk_ctx* c, AdjArgs& a, int kb, int64_t top, double t_start, bool inject) {
+    const Geometry& geo = c->geo;
+    a.kb = kb;
+    a.n_strips = (int)((geo.nr + (WAVE - 2 * kb) - 1) / (WAVE - 2 * kb));
+    for (int k = 0; k < KB_MAX; ++k) {
+        const int64_t step = top - 1 - k;   // forward step reversed by stage k
+        const double t0 = t_start + double(step) * c->dt, t1 = t0 + 0.5 * c->dt;
+        const double w0 = geo.m * c->Omega * t0, w1 = geo.m * c->Omega * t1;
+        a.t[2 * k] = t0;
+        a.t[2 * k + 1] = t1;
+        a.ph[2 * k][0] = std::cos(w0);
+        a.ph[2 * k][1] = -std::sin(w0);
+        a.ph[2 * k + 1][0] = std::cos(w1);
+        a.ph[2 * k + 1][1] = -std::sin(w1);
+        a.g_row[k] = (inject && k < kb) ? step : -1;
+    }
+}
+
+int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t n, double t_start, char* ws,
+                  double* dphi0, double* dpi0, double* res_host) {
+    const Geometry& geo = c->geo;
+    const AdjLayout lay = adjoint_layout(c);
+    const int64_t npts = geo.nr * geo.nth;
+    const int64_t n_slots = adjoint_slots_used(c);
+    double* wl[2] = {(double*)(ws + lay.lam), (double*)(ws + lay.lam) + 2 * npts};
+    double* slots = (double*)(ws + lay.slots);
+    double* result = (double*)(ws + lay.result);
+    // launches from the top: kb steps each, the odd remainder last
+    std::vector<int> plan;
+    for (int64_t r = n; r > 0;) {
+        const int kb = (c->adj_kb >= 2 && r >= 2) ? 2 : 1;
+        plan.push_back(kb);
+        r -= kb;
+    }
+    // start in the pair that makes the last launch write (dphi0, dpi0)
+    double* pair[2][2] = {{dphi0, dpi0}, {wl[0], wl[1]}};
+    int cur = (plan.size() % 2 == 1) ? 1 : 0;
+    launch_adjoint_init(pair[cur][0], pair[cur][1], g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    launch_fill_zero(slots, n_slots * 3, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    AdjArgs a = adjoint_args(c, g, iobs, alpha, slots);
     int64_t top = n;   // this launch reads lambda^top
     for (int kb : plan) {
-        a.kb = kb;
-        a.n_strips = (int)((geo.nr + (WAVE - 2 * kb) - 1) / (WAVE - 2 * kb));
-        for (int k = 0; k < KB_MAX; ++k) {
-            const int64_t step = top - 1 - k;   // forward step reversed by stage k
-            const double t0 = t_start + double(step) * c->dt, t1 = t0 + 0.5 * c->dt;
-            const double w0 = geo.m * c->Omega * t0, w1 = geo.m * c->Omega * t1;
-            a.t[2 * k] = t0;
-            a.t[2 * k + 1] = t1;
-            a.ph[2 * k][0] = std::cos(w0);
-            a.ph[2 * k][1] = -std::sin(w0);
-            a.ph[2 * k + 1][0] = std::cos(w1);
-            a.ph[2 * k + 1][1] = -std::sin(w1);
-            a.g_row[k] = (k < kb) ? step : -1;
-        }
+        adjoint_launch_args(c, a, kb, top, t_start, true);
         a.lp = pair[cur][0];
         a.lq = pair[cur][1];
         a.lp_out = pair[1 - cur][0];
@@ -307,11 +337,50 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
         cur = 1 - cur;
         top -= kb;
     }
-    launch_slot_sum(slots, lay.n_slots, result, c->stream);
+    launch_slot_sum(slots, n_slots, result, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(res_host, result, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TEUK_OK;
+}
+
+// Seconds per reverse step of `launches` trial launches at the context's
+// reverse-sweep tiling.  The trial reads the bound state's current pair as
+// lambda and writes the other pair, which is scratch between forward steps,
+// so the state, the step count and the waveform are left as they were; the
+// gradient slots go to `slots` (room for adjoint_slots_max entries).
+int adjoint_time_trial(teuk_ctx* c, int launches, double* slots, double* sec_per_step) {
+    const int kb = c->adj_kb;
+    launch_fill_zero(slots, adjoint_slots_used(c) * 3, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    AdjArgs a = adjoint_args(c, nullptr, 0, 0.0, slots);
+    adjoint_launch_args(c, a, kb, kb, 0.0, false);
+    a.lp = (const double*)c->buf[c->cur][0];
+    a.lq = (const double*)c->buf[c->cur][1];
+    a.lp_out = (double*)c->buf[1 - c->cur][0];
+    a.lq_out = (double*)c->buf[1 - c->cur][1];
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, TEUK_EDEVICE, "hipEventCreate failed");
+    }
+    int rc = TEUK_OK;
+    launch_adjoint_step(a, c->stream);   // warm-up
+    if (hipGetLastError() != hipSuccess) rc = fail(c, TEUK_EDEVICE, "reverse-step launch failed");
+    if (rc == TEUK_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, TEUK_EDEVICE, "event record");
+    for (int k = 0; rc == TEUK_OK && k < launches; ++k) {
+        launch_adjoint_step(a, c->stream);
+        if (hipGetLastError() != hipSuccess) rc = fail(c, TEUK_EDEVICE, "reverse-step launch failed");
+    }
+    if (rc == TEUK_OK && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, TEUK_EDEVICE, "event record");
+    float ms = 0.0f;
+    if (rc == TEUK_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(c, TEUK_EDEVICE, "event timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == TEUK_OK) *sec_per_step = 1e-3 * ms / double(launches * kb);
+    return rc;
 }
 
 }  // namespace
@@ -619,6 +688,75 @@ int teuk_get_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* order) {
     if (!c) return TEUK_EINVAL;
     if (rows_per_wave) *rows_per_wave = c->rows;
     if (order) *order = c->order;
+    return TEUK_OK;
+}
+
+int teuk_set_adjoint_tiling(teuk_ctx* c, int32_t rows_per_wave, int32_t steps_per_launch) {
+    if (!c) return TEUK_EINVAL;
+    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(c, TEUK_EINVAL, "rows_per_wave out of range");
+    if (steps_per_launch < 1 || steps_per_launch > KB_MAX)
+        return fail(c, TEUK_EINVAL, "steps_per_launch must be 1..%d", KB_MAX);
+    c->adj_rows = rows_per_wave;
+    c->adj_kb = steps_per_launch;
+    return TEUK_OK;
+}
+
+int teuk_get_adjoint_tiling(teuk_ctx* c, int32_t* rows_per_wave, int32_t* steps_per_launch) {
+    if (!c) return TEUK_EINVAL;
+    if (rows_per_wave) *rows_per_wave = adjoint_rows(c);
+    if (steps_per_launch) *steps_per_launch = c->adj_kb;
+    return TEUK_OK;
+}
+
+static int adjoint_autotune_trials(teuk_ctx* c, int32_t launches_per_trial, double* slots, int* best_rows,
+                                   int* best_kb) {
+    static const int kRows[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const int nth = (int)c->geo.nth;
+    double best = 0.0;
+    for (int kb = 1; kb <= KB_MAX; ++kb) {
+        int prev = 0;
+        for (int r : kRows) {
+            const int rows = std::min(r, nth);
+            if (rows == prev) continue;   // candidates clipped to n_theta repeat
+            prev = rows;
+            c->adj_rows = rows;
+            c->adj_kb = kb;
+            double sec = 0.0;
+            const int rc = adjoint_time_trial(c, launches_per_trial, slots, &sec);
+            if (rc != TEUK_OK) return rc;
+            if (best == 0.0 || sec < best) {
+                best = sec;
+                *best_rows = rows;
+                *best_kb = kb;
+            }
+        }
+    }
+    return TEUK_OK;
+}
+
+int teuk_adjoint_autotune(teuk_ctx* c, int32_t launches_per_trial, int32_t* rows_out, int32_t* kb_out) {
+    if (!c) return TEUK_EINVAL;
+    if (c->status != TEUK_OK) return c->status;
+    if (c->prec != TEUK_FP64) return fail(c, TEUK_ENOTSUP, "the reverse sweep is FP64 only");
+    if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
+    if (launches_per_trial < 1 || launches_per_trial > 10000)
+        return fail(c, TEUK_EINVAL, "launches_per_trial must be 1..10000");
+    double* slots = nullptr;
+    HIP_TRY(c, hipMalloc((void**)&slots, adjoint_slots_max(c->geo) * 3 * sizeof(double)));
+    const int keep_rows = c->adj_rows, keep_kb = c->adj_kb;
+    int best_rows = adjoint_rows(c), best_kb = keep_kb;
+    const int rc = adjoint_autotune_trials(c, launches_per_trial, slots, &best_rows, &best_kb);
+    (void)hipStreamSynchronize(c->stream);   // the trials are done with the slots
+    (void)hipFree(slots);
+    if (rc != TEUK_OK) {
+        c->adj_rows = keep_rows;
+        c->adj_kb = keep_kb;
+        return rc;
+    }
+    c->adj_rows = best_rows;
+    c->adj_kb = best_kb;
+    if (rows_out) *rows_out = best_rows;
+    if (kb_out) *kb_out = best_kb;
     return TEUK_OK;
 }
 

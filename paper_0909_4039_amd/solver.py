@@ -151,6 +151,28 @@ class Solver:
         check(_lib.lib().teuk_get_tiling(self._ctx, ctypes.byref(r), ctypes.byref(o)), self._ctx)
         return r.value, o.value
 
+    def set_adjoint_tiling(self, rows_per_wave=0, steps_per_launch=1):
+        """Tile shape of the reverse sweep (rows 0: follow the step kernel's)."""
+        check(_lib.lib().teuk_set_adjoint_tiling(self._ctx, int(rows_per_wave), int(steps_per_launch)), self._ctx)
+
+    def get_adjoint_tiling(self):
+        r = ctypes.c_int32()
+        k = ctypes.c_int32()
+        check(_lib.lib().teuk_get_adjoint_tiling(self._ctx, ctypes.byref(r), ctypes.byref(k)), self._ctx)
+        return r.value, k.value
+
+    def adjoint_workspace_bytes(self):
+        return check_int(_lib.lib().teuk_adjoint_workspace_bytes(self._ctx))
+
+    def adjoint_autotune(self, launches_per_trial=10):
+        """Pick the fastest reverse-sweep tiling by timing trial reverse steps
+        on the bound state (left unchanged); returns (rows, steps_per_launch)."""
+        r = ctypes.c_int32()
+        k = ctypes.c_int32()
+        check(_lib.lib().teuk_adjoint_autotune(self._ctx, int(launches_per_trial), ctypes.byref(r),
+                                               ctypes.byref(k)), self._ctx)
+        return r.value, k.value
+
     def adjoint(self, dL_dwave, n_steps, rstar_obs, t_start=0.0):
         """Reverse sweep of the library (FP64): gradients of a real loss of the
         waveform w^0..w^n recorded at rstar_obs from initial data at t_start.
@@ -163,7 +185,7 @@ class Solver:
         g = torch.as_tensor(dL_dwave).to(self.device, torch.complex128).contiguous()
         if g.shape != (n + 1, self.shape[0]):
             raise ValueError(f"dL_dwave has shape {tuple(g.shape)}, expected {(n + 1, self.shape[0])}")
-        nbytes = check_int(_lib.lib().teuk_adjoint_workspace_bytes(self._ctx))
+        nbytes = self.adjoint_workspace_bytes()
         ws = torch.empty((nbytes + 255) // 8 + 32, dtype=torch.float64, device=self.device)
         base = ws.data_ptr()
         off = (-base) % 256

@@ -33,6 +33,9 @@ def make_solver(case, dt, kb=None, rows=None, order=0):
         s.set_blocking(kb)
     if rows:
         s.set_tiling(rows, order)
+    if kb is not None or rows:
+        # the reverse sweep's own tiling: these rows (0 follows the forward's)
+        s.set_adjoint_tiling(rows or 0, kb or 1)
     if case.get("r0"):
         s.set_source(case["r0"], case.get("amp", 0.0))
     return s
@@ -121,6 +124,42 @@ def test_adjoint_bitwise_across_tilings(oracle_mod):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (kb, rows)
         # the source-gradient sums group their terms by tile: equal to rounding
         assert rel_scalar(got[2], ref[2]) <= 1e-13 and rel_scalar(got[3], ref[3]) <= 1e-13
+
+
+def test_adjoint_tiling_setters_and_autotune(oracle_mod):
+    import torch
+    case = CASES[3]
+    dt = _dt(oracle_mod, case)
+    n = 33
+    g = seeded_g(n, case["nth"], seed=9)
+    ref = gpu_adjoint(case, dt, g, n, kb=1, rows=1)
+    s = make_solver(case, dt)
+    assert s.get_adjoint_tiling() == (s.get_tiling()[0], 1)     # defaults: forward rows, one step
+    s.set_tiling(12)
+    assert s.get_adjoint_tiling() == (12, 1)
+    ws0 = s.adjoint_workspace_bytes()
+    s.set_adjoint_tiling(3, 2)
+    assert s.get_adjoint_tiling() == (3, 2) and s.adjoint_workspace_bytes() == ws0
+    from paper_0909_4039_amd import TeukError
+    for bad in ((-1, 1), (4097, 1), (8, 0), (8, 3)):
+        with pytest.raises(TeukError):
+            s.set_adjoint_tiling(*bad)
+    assert s.get_adjoint_tiling() == (3, 2)
+    # the trials read the current pair and write the other: the state stays
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=4)
+    s.set_state(phi, pi)
+    s.step(3)
+    torch.cuda.synchronize()
+    keep = (s.phi.clone(), s.pi.clone(), s.get_time())
+    rows, kb = s.adjoint_autotune(2)
+    print(f"[gpu] adjoint autotune picked rows={rows} kb={kb}", flush=True)
+    assert s.get_adjoint_tiling() == (rows, kb) and 1 <= kb <= 2
+    torch.cuda.synchronize()
+    assert torch.equal(s.phi, keep[0]) and torch.equal(s.pi, keep[1]) and s.get_time() == keep[2]
+    dphi, dpi, dr0, damp = s.adjoint(g, n, case["robs"])
+    assert np.array_equal(dphi.cpu().numpy(), ref[0]) and np.array_equal(dpi.cpu().numpy(), ref[1])
+    assert rel_scalar(dr0, ref[2]) <= 1e-13 and rel_scalar(damp, ref[3]) <= 1e-13
+    s.close()
 
 
 @pytest.mark.parametrize("robs_index", [59, 60, 61, 62, 119, 120])
