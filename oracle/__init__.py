@@ -81,6 +81,7 @@ def _L():
             "teuko_Omega": (D, [P]), "teuko_iobs": (I64, [P]), "teuko_alpha": (D, [P]),
             "teuko_max_DoS2": (D, [P]),
             "teuko_set_trajectory": (ctypes.c_int, [P, P, I64, D]),
+            "teuko_adjoint_run_moving": (ctypes.c_int, [P, P, I64, P, P, P, ctypes.POINTER(D)]),
             "teuko_threads": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -229,6 +230,22 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle adjoint failed")
         return d1, d2, r0.value, am.value
+
+
+    def adjoint_run_moving(self, g, n):
+        """Reverse sweep for the orbit table of ``set_trajectory``, the forward
+        run starting at its first entry: returns dphi0, dpi0, dL/dtraj
+        ((2n, 2): dL/dr0_e, dL/dphi_e for entries e < 2n) and dL/damp."""
+        g = np.ascontiguousarray(g, dtype=np.complex128)
+        assert g.shape == (n + 1, self.shape[0])
+        d1, d2 = np.empty(self.shape, np.complex128), np.empty(self.shape, np.complex128)
+        dtraj = np.zeros((2 * n, 2), dtype=np.float64)
+        am = ctypes.c_double(0.0)
+        rc = _L().teuko_adjoint_run_moving(self._c, _ptr(g), int(n), _ptr(d1), _ptr(d2), _ptr(dtraj),
+                                           ctypes.byref(am))
+        if rc != 0:
+            raise ValueError("oracle moving-source adjoint failed (no table, or it is too short)")
+        return d1, d2, dtraj, am.value
 
 
 def stable_dt(nr, nth, rstar_min, rstar_max, a, M, m, s, n_steps) -> float:

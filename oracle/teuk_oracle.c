@@ -58,7 +58,8 @@
  *   - Waveform: linear interpolation of Phi in r* at r*_obs, for every theta.
  *   - Adjoint: the exact transpose of one step in the real 4-component view
  *     (Eq. 9), written out by hand in reverse order, and the source-parameter
- *     gradients it induces.
+ *     gradients it induces: dL/dr0 and dL/damp for the static source, and
+ *     dL/dr0_e, dL/dphi_e for every entry e of a moving source's orbit table.
  *
  * The grid may be held as a window (rows j0..j0+nj-1, columns i0..i0+ni-1 of
  * the full grid).  A neighbour that lies inside the full grid but outside the
@@ -68,8 +69,9 @@
  * Parity status: the coefficient forms, the angular operator, the tortoise
  * map, the scheme's order of accuracy, the Schwarzschild l=2 ringdown, the
  * Kerr a = 0.5 l = m = 2 ringdown (which depends on every a-dependent
- * coefficient), the m -> -m mirror symmetry and the adjoint are pinned by
- * tests.  Kerr pointwise values have no printed reference; they are pinned
+ * coefficient), the m -> -m mirror symmetry, the adjoint and the
+ * moving-source gradients (central differences of the forward run) are
+ * pinned by tests.  Kerr pointwise values have no printed reference; they are pinned
  * through the Kerr ringdown and the invariants above.
  */
 #include <complex.h>
@@ -353,15 +355,20 @@ int teuko_set_trajectory(teuko_ctx* c, const double* r0_phi, int64_t n_half, dou
     return 0;
 }
 
-/* T at column ii, row jj of a point at r* = xs for an orbit at (r0, phi):
-   amp exp(-(r* - r*(r0))^2 / (2 sr^2)) exp(-(th - pi/2)^2 / (2 sth^2)) e^{-i m phi}. */
-static cplx moving_T(const teuko_ctx* c, double xs, int64_t jj, double r0, double phi) {
+/* Unit-amplitude source at row jj of a point at r* = xs for an orbit at
+   (r0, phi): exp(-(r* - r*(r0))^2 / (2 sr^2)) exp(-(th - pi/2)^2 / (2 sth^2)) e^{-i m phi}. */
+static cplx moving_unit(const teuko_ctx* c, double xs, int64_t jj, double r0, double phi) {
     const teuko_params* p = &c->p;
     double sr = p->sigma_r_cells * c->dr, st = p->sigma_th_cells * c->dth;
     double x = xs - teuko_rstar_of_r(r0, p->a, p->M);
     double th = c->th[jj];
     double gth = exp(-(th - 0.5 * M_PI) * (th - 0.5 * M_PI) / (2.0 * st * st));
-    return p->amp * (exp(-x * x / (2.0 * sr * sr)) * gth) * cexp(-I * (double)p->m * phi);
+    return (exp(-x * x / (2.0 * sr * sr)) * gth) * cexp(-I * (double)p->m * phi);
+}
+
+/* T = amp times the unit source. */
+static cplx moving_T(const teuko_ctx* c, double xs, int64_t jj, double r0, double phi) {
+    return c->p.amp * moving_unit(c, xs, jj, r0, phi);
 }
 
 int teuko_step(teuko_ctx* c, const double* phi_ri, const double* pi_ri,
@@ -661,6 +668,81 @@ int teuko_adjoint_run(teuko_ctx* c, const double* g_ri, int64_t n, double t_star
     memcpy(dphi0_ri, lP, sizeof(cplx) * N);
     memcpy(dpi0_ri, lQ, sizeof(cplx) * N);
     *dL_dr0 = gr0;
+    *dL_damp = gam;
+    free(lP); free(lQ); free(nP); free(nQ); free(aTh); free(aTi);
+    return 0;
+}
+
+/* Moving-source gradients of one stage: table entry (r0, phi) with the
+   source adjoint a at half (half = 1) or integer points.  With
+   T = amp rho(r*) gth(th) e^{-i m phi}, rho = exp(-x^2 / (2 sr^2)),
+   x = r* - r*(r0), and U = T / amp the unit-amplitude source:
+     dT/damp = U,
+     dT/dr0  = T (x / sr^2) (d r* / d r)(r0),  with d r* / d r = (r^2 + a^2) / Delta (Eq. 2),
+     dT/dphi = -i m T,
+   each contracted as Re sum conj(a) dT/dp. */
+static void moving_grad(const teuko_ctx* c, const cplx* a, int half, const double* entry,
+                        double* g_r0, double* g_phi, double* g_amp) {
+    const teuko_params* p = &c->p;
+    int64_t ni = p->ni, nj = p->nj;
+    double sr = p->sigma_r_cells * c->dr;
+    double r0 = entry[0], phi = entry[1];
+    double drs0_dr0 = (r0 * r0 + p->a * p->a) / (r0 * r0 - 2.0 * p->M * r0 + p->a * p->a);
+    double sa = 0.0, sr0 = 0.0, sph = 0.0;
+    for (int64_t jj = 0; jj < nj; ++jj)
+        for (int64_t ii = 0; ii < ni; ++ii) {
+            double xs = p->rstar_min + (p->i0 + ii + (half ? 0.5 : 0.0)) * c->dr;
+            double x = xs - teuko_rstar_of_r(r0, p->a, p->M);
+            cplx U = moving_unit(c, xs, jj, r0, phi);
+            cplx ca = conj(a[jj * ni + ii]);
+            sa += creal(ca * U);
+            sr0 += creal(ca * (p->amp * U) * ((x / (sr * sr)) * drs0_dr0));
+            sph += creal(ca * (-I * (double)p->m) * (p->amp * U));
+        }
+    *g_r0 += sr0;
+    *g_phi += sph;
+    *g_amp += sa;
+}
+
+/* Reverse sweep for a moving source: as teuko_adjoint_run, for a forward
+   run of n steps from the first entry of the orbit table (step k used
+   entries 2k and 2k+1).  Returns dL/dPhi0, dL/dPi0, dL/damp and, for every
+   entry e < 2n, dL/dr0_e and dL/dphi_e in dL_dtraj[2e], dL_dtraj[2e+1]. */
+int teuko_adjoint_run_moving(teuko_ctx* c, const double* g_ri, int64_t n, double* dphi0_ri, double* dpi0_ri,
+                             double* dL_dtraj, double* dL_damp) {
+    if (!c->traj || 2 * n > c->traj_n) return -1;
+    const teuko_params* p = &c->p;
+    int64_t ni = p->ni, nj = p->nj, N = ni * nj;
+    const cplx* g = (const cplx*)g_ri;
+    int64_t k0 = c->iobs - p->i0;
+    if (k0 < 0 || k0 + 1 >= ni) return -1;
+    cplx* lP = (cplx*)calloc(N, sizeof(cplx));
+    cplx* lQ = (cplx*)calloc(N, sizeof(cplx));
+    cplx* nP = (cplx*)calloc(N, sizeof(cplx));
+    cplx* nQ = (cplx*)calloc(N, sizeof(cplx));
+    cplx* aTh = (cplx*)calloc(N, sizeof(cplx));
+    cplx* aTi = (cplx*)calloc(N, sizeof(cplx));
+    double gam = 0.0;
+    for (int64_t e = 0; e < 2 * n; ++e) { dL_dtraj[2 * e] = 0.0; dL_dtraj[2 * e + 1] = 0.0; }
+    for (int64_t jj = 0; jj < nj; ++jj) {
+        lP[jj * ni + k0] += (1.0 - c->alpha) * g[n * nj + jj];
+        lP[jj * ni + k0 + 1] += c->alpha * g[n * nj + jj];
+    }
+    for (int64_t k = n - 1; k >= 0; --k) {
+        teuko_adjoint_step(c, (double*)lP, (double*)lQ, (double*)nP, (double*)nQ, (double*)aTh, (double*)aTi);
+        /* predictor: entry 2k on half points; corrector: entry 2k+1 on integer points */
+        moving_grad(c, aTh, 1, c->traj + 2 * (2 * k), &dL_dtraj[2 * (2 * k)], &dL_dtraj[2 * (2 * k) + 1], &gam);
+        moving_grad(c, aTi, 0, c->traj + 2 * (2 * k + 1), &dL_dtraj[2 * (2 * k + 1)],
+                    &dL_dtraj[2 * (2 * k + 1) + 1], &gam);
+        for (int64_t jj = 0; jj < nj; ++jj) {
+            nP[jj * ni + k0] += (1.0 - c->alpha) * g[k * nj + jj];
+            nP[jj * ni + k0 + 1] += c->alpha * g[k * nj + jj];
+        }
+        cplx* t1 = lP; lP = nP; nP = t1;
+        cplx* t2 = lQ; lQ = nQ; nQ = t2;
+    }
+    memcpy(dphi0_ri, lP, sizeof(cplx) * N);
+    memcpy(dpi0_ri, lQ, sizeof(cplx) * N);
     *dL_damp = gam;
     free(lP); free(lQ); free(nP); free(nQ); free(aTh); free(aTi);
     return 0;
