@@ -95,8 +95,8 @@ int teuk_set_source(teuk_ctx* ctx, double r0, double amp, double sigma_r_cells,
  * t^n + dt/2 (corrector); teuk_step fails with TEUK_EINVAL past the table.
  * With r0 fixed and phi = Omega t it is the fixed-orbit source up to
  * rounding.  r0_phase = NULL returns to the fixed orbit.  Requires
- * teuk_set_source first (TEUK_ESTATE) and r0 > r+ in every entry.  The
- * reverse sweep refuses a context with a trajectory (TEUK_ENOTSUP). */
+ * teuk_set_source first (TEUK_ESTATE) and r0 > r+ in every entry.  Its
+ * reverse sweep is teuk_adjoint_moving. */
 int teuk_set_trajectory(teuk_ctx* ctx, const double* r0_phase, int64_t n_half);
 
 /* Waveform recorder: from now on each step records
@@ -116,7 +116,9 @@ int teuk_step(teuk_ctx* ctx, int64_t n);
  * (device, n_theta complex). */
 int teuk_extract(teuk_ctx* ctx, double rstar_obs, void* out);
 
-/* Host-side time bookkeeping: t = t0 + (step - step0) dt. */
+/* Host-side time bookkeeping: t = t0 + (step - step0) dt.  teuk_set_time
+ * relabels the current step; the observer's rows and the orbit table of
+ * teuk_set_trajectory stay attached to the same steps. */
 int teuk_get_time(teuk_ctx* ctx, double* t, int64_t* step);
 int teuk_set_time(teuk_ctx* ctx, double t, int64_t step);
 
@@ -160,13 +162,38 @@ int teuk_get_blocking(teuk_ctx* ctx);
  *   dL_dr0, dL_damp: host, may be NULL; both 0 if no source was set.
  * Uses the context's dt, source and reverse-sweep tiling
  * (teuk_set_adjoint_tiling), and neither reads nor changes the bound state
- * or the time.  The workspace size does not depend on the tiling.  Synchronous (returns
- * after the sweep).  TEUK_ENOTSUP for FP32 contexts; TEUK_EINVAL for
+ * or the time.  The workspace size does not depend on the tiling.
+ * Synchronous (returns after the sweep).  TEUK_ENOTSUP for FP32 contexts and while an orbit
+ * table is set (its sweep is teuk_adjoint_moving); TEUK_EINVAL for
  * misaligned, overlapping or short buffers or rstar_obs outside the grid. */
 int64_t teuk_adjoint_workspace_bytes(teuk_ctx* ctx);
 int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
                  void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
                  double* dL_damp);
+
+/* Reverse sweep for a moving source (FP64; the orbit table of
+ * teuk_set_trajectory).  As teuk_adjoint, for a forward run of n_steps
+ * steps from initial data u^0 that started at the table's first entry, so
+ * that step k used entry 2k (predictor, t^k) and entry 2k + 1 (corrector,
+ * t^k + dt/2).  With T = amp U, U = exp(-(r* - r*(r0_e))^2 / 2 sr^2)
+ * G_theta e^{-i m phi_e} the unit-amplitude source of entry e (the moving
+ * source that stands in for the paper's T on a decaying orbit, Fig. 1):
+ *   dL/dr0_e  = Re sum conj(a_T) amp U (r* - r*(r0_e)) / sr^2 (d r* / d r)(r0_e),
+ *   dL/dphi_e = Re sum conj(a_T) (-i m) amp U,
+ *   dL/damp   = Re sum over all entries and points of conj(a_T) U,
+ * with d r* / d r = (r^2 + a^2)/Delta (Eq. 2).  The partial sums of every
+ * launch are reduced in a fixed order, so results repeat bit for bit.
+ *   dL_dtraj: host, 2 n_steps x 2 doubles (written): row e = (dL/dr0_e,
+ *     dL/dphi_e); entries from 2 n_steps on are not read by the run and
+ *     have zero gradient.
+ *   dL_damp: host, may be NULL.
+ * Other arguments as teuk_adjoint (no t_start: the table fixes the phases).
+ * The workspace size (teuk_adjoint_workspace_bytes) grows with the table,
+ * so query it after teuk_set_trajectory.  TEUK_ESTATE without a table;
+ * TEUK_EINVAL if 2 n_steps exceeds the table length or for bad buffers;
+ * TEUK_ENOTSUP for FP32 contexts. */
+int teuk_adjoint_moving(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t n_steps, void* workspace,
+                        int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dtraj, double* dL_damp);
 
 /* Autotuner (synchronous): times launches_per_trial launches (after one
  * warm-up launch) of every candidate tile shape -- theta rows per wavefront

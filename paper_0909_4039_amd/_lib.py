@@ -56,6 +56,8 @@ _SIGS = {
                                     ctypes.POINTER(_D)]),
     "teuk_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_set_adjoint_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "teuk_adjoint_moving": (ctypes.c_int, [_P, ctypes.c_double, _P, _I64, _P, _I64, _P, _P, _P,
+                                           ctypes.POINTER(ctypes.c_double)]),
     "teuk_get_adjoint_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_adjoint_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_batch_create": (ctypes.c_int, [_I32, ctypes.POINTER(TeukDesc), _I64, _P, ctypes.POINTER(_P)]),

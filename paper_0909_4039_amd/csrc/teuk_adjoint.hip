@@ -143,10 +143,19 @@ struct AStep {
     C ph0, ph1;            // e^{-i m Omega t}, e^{-i m Omega (t + dt/2)}
     double t0, t1;
     const double* grow;    // g row injected into this stage's output (NULL: none)
+    // moving source: this lane's radial Gaussian and log-derivative
+    // (r* - r*0) / sr^2 for the predictor's (0, half point) and the
+    // corrector's (1, integer point) table entry
+    double rho0, x0, rho1, x1;
 };
 
+// acc_h / acc_i take the source-gradient terms of the predictor (half
+// points) and of the corrector (integer points); the static source passes
+// one accumulator for both.
+template <bool MOV>
 __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AStep& S, int L, C p, C q,
-                                           GradAcc& acc, C& outP, bool& okP, C& outQ, bool& okQ) {
+                                           GradAcc& acc_h, GradAcc& acc_i, C& outP, bool& okP, C& outQ,
+                                           bool& okQ) {
     const double half = 0.5;
     const C zero = {0.0, 0.0};
     const int H = L - 1, R = L - 2;
@@ -167,8 +176,12 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
         C hi = rfma(-K.idr, o.adg, half * o.ag);
         ahqL = lo + shfl_dn1(hi);
         const double gth = load_gth(K.ang, L);
-        if (K.own_col && L >= K.own_lo && L < K.own_hi && gth != 0.0)
-            grad_add(acc, K.dt, yQ, gth, qi.gr, K.xr_i[K.cu], S.ph1, S.t1);
+        if (K.own_col && L >= K.own_lo && L < K.own_hi && gth != 0.0) {
+            if constexpr (MOV)
+                grad_add(acc_i, K.dt, yQ, gth, S.rho1, S.x1, S.ph1, 1.0);
+            else
+                grad_add(acc_i, K.dt, yQ, gth, qi.gr, K.xr_i[K.cu], S.ph1, S.t1);
+        }
     }
     // ---- B: reverse predictor at half row H
     C bpbR = st.bpb, bpbH = zero, bdpH = zero, th = zero;
@@ -192,8 +205,12 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
             outQ = st.yq1 + lo + shfl_up1(hi);
         }
         const double gth = load_gth(K.ang, H);
-        if (K.own_col && H >= K.own_lo && H < K.own_hi && gth != 0.0)
-            grad_add(acc, K.hdt, ahq, gth, qh.gr, K.xr_h[K.cu], S.ph0, S.t0);
+        if (K.own_col && H >= K.own_lo && H < K.own_hi && gth != 0.0) {
+            if constexpr (MOV)
+                grad_add(acc_h, K.hdt, ahq, gth, S.rho0, S.x0, S.ph0, 1.0);
+            else
+                grad_add(acc_h, K.hdt, ahq, gth, qh.gr, K.xr_h[K.cu], S.ph0, S.t0);
+        }
     }
     // ---- C: Phi adjoint of output row R
     okP = (R >= st.olo && R < st.ohi);
@@ -220,7 +237,7 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
     st.yq1 = yQ;
 }
 
-template <int KB>
+template <int KB, bool MOV>
 __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, const double* __restrict__ lq,
                                               double* __restrict__ lp_out, double* __restrict__ lq_out,
                                               const double* __restrict__ rad_i, const double* __restrict__ rad_h,
@@ -233,7 +250,11 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     const int chunk = blk / ngrp;
     const int grp = blk - chunk * ngrp;
     const int strip = grp * WG_WAVES + wid;
-    if (strip >= A.n_strips) return;   // wave-uniform; the kernel has no barriers
+    if (strip >= A.n_strips) {   // wave-uniform; the kernel has no barriers
+        if (MOV && (threadIdx.x & (WAVE - 1)) < 6 * KB)   // this wave's per-launch slot holds zeros
+            A.mslots[((int64_t)blockIdx.x * WG_WAVES + wid) * (6 * KB) + (threadIdx.x & (WAVE - 1))] = 0.0;
+        return;
+    }
     const int nr = A.nr, nth = A.nth;
     const int c = strip * SO - KB + lane;
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
@@ -277,6 +298,15 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
         S[k].t0 = A.t[2 * k];
         S[k].t1 = A.t[2 * k + 1];
         S[k].grow = A.g_row[k] >= 0 ? A.g + 2 * A.g_row[k] * (int64_t)nth : nullptr;
+        S[k].rho0 = S[k].x0 = S[k].rho1 = S[k].x1 = 0.0;
+        if constexpr (MOV) {
+            const double xh = fma((double)c + 0.5, A.dr, A.rmin) - A.rs0[2 * k];
+            const double xi = fma((double)c, A.dr, A.rmin) - A.rs0[2 * k + 1];
+            S[k].rho0 = exp((-xh * xh) / A.two_sr2);
+            S[k].rho1 = exp((-xi * xi) / A.two_sr2);
+            S[k].x0 = xh * A.inv_sr2;
+            S[k].x1 = xi * A.inv_sr2;
+        }
     }
     APipe st[KB];
 #pragma unroll
@@ -289,6 +319,9 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
 #pragma unroll
     for (int k = 0; k < KB; ++k) heldQ[k] = zero;
     GradAcc acc = {0.0, 0.0, 0.0};
+    GradAcc macc[MOV ? 2 * KB : 1];   // moving source: [2k] predictor, [2k + 1] corrector of stage k
+#pragma unroll
+    for (int e = 0; e < (MOV ? 2 * KB : 1); ++e) macc[e] = {0.0, 0.0, 0.0};
 
     C pf_p = ld_row_once(lp, (int64_t)Ls * nr, boff), pf_q = ld_row_once(lq, (int64_t)Ls * nr, boff);
 
@@ -306,7 +339,10 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
             const int Lk = L - 2 * k;
             C oP = zero, oQ = zero;
             bool okP, okQ;
-            apipe_iter(st[k], K, S[k], Lk, p, q, acc, oP, okP, oQ, okQ);
+            if constexpr (MOV)
+                apipe_iter<true>(st[k], K, S[k], Lk, p, q, macc[2 * k], macc[2 * k + 1], oP, okP, oQ, okQ);
+            else
+                apipe_iter<false>(st[k], K, S[k], Lk, p, q, acc, acc, oP, okP, oQ, okQ);
             if (k == KB - 1) {
                 if (okQ && out_lane) st_row(lq_out, (int64_t)(Lk - 1) * nr, soff, oQ);
                 if (okP && out_lane) st_row(lp_out, (int64_t)(Lk - 2) * nr, soff, oP);
@@ -323,6 +359,24 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
         iter(L);
         iter(L + 1);
     }
+    if constexpr (MOV) {
+        // wave sums of every entry in a fixed butterfly order, written into
+        // this launch's slot of the wave
+        double* slot = A.mslots + ((int64_t)blockIdx.x * WG_WAVES + wid) * (6 * KB);
+#pragma unroll
+        for (int e = 0; e < 2 * KB; ++e) {
+            double v[3] = {macc[e].sa, macc[e].sx, macc[e].st};
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, WAVE);
+            if (lane == 0) {
+                slot[3 * e + 0] = v[0];
+                slot[3 * e + 1] = v[1];
+                slot[3 * e + 2] = v[2];
+            }
+        }
+        return;
+    }
     // wave sums in a fixed butterfly order, added into this wave's slot
     double v[3] = {acc.sa, acc.sx, acc.st};
 #pragma unroll
@@ -336,30 +390,69 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     }
 }
 
+#define ADJ_PARAMS                                                                                  \
+    const double* __restrict__ lp, const double* __restrict__ lq, double* __restrict__ lp_out,    \
+        double* __restrict__ lq_out, const double* __restrict__ rad_i, const double* __restrict__ rad_h, \
+        const double* __restrict__ ang, AdjArgs A
+
 // One reverse step per launch fits 4 waves per SIMD (128 VGPRs, no spills);
-// two fused steps need more registers and run at 2.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void adj_step_kernel1(
-    const double* __restrict__ lp, const double* __restrict__ lq, double* __restrict__ lp_out,
-    double* __restrict__ lq_out, const double* __restrict__ rad_i, const double* __restrict__ rad_h,
-    const double* __restrict__ ang, AdjArgs A) {
-    adj_step_body<1>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+// two fused steps need more registers and run at 2.  The moving-source
+// variants keep per-entry sums and run at the occupancy their registers allow.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void adj_step_kernel1(ADJ_PARAMS) {
+    adj_step_body<1, false>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
 }
-__global__ __launch_bounds__(256) void adj_step_kernel2(const double* __restrict__ lp, const double* __restrict__ lq,
-                                                       double* __restrict__ lp_out, double* __restrict__ lq_out,
-                                                       const double* __restrict__ rad_i,
-                                                       const double* __restrict__ rad_h,
-                                                       const double* __restrict__ ang, AdjArgs A) {
-    adj_step_body<2>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+__global__ __launch_bounds__(256) void adj_step_kernel2(ADJ_PARAMS) {
+    adj_step_body<2, false>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
 }
+__global__ __launch_bounds__(256) void adj_step_kernel1_moving(ADJ_PARAMS) {
+    adj_step_body<1, true>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+}
+__global__ __launch_bounds__(256) void adj_step_kernel2_moving(ADJ_PARAMS) {
+    adj_step_body<2, true>(lp, lq, lp_out, lq_out, rad_i, rad_h, ang, A);
+}
+#undef ADJ_PARAMS
 
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s) {
     int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
-    if (a.kb == 2)
-        hipLaunchKernelGGL(adj_step_kernel2, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
-                           a.lq_out, a.rad_i, a.rad_h, a.ang, a);
-    else
-        hipLaunchKernelGGL(adj_step_kernel1, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out,
-                           a.lq_out, a.rad_i, a.rad_h, a.ang, a);
+    auto kern = a.moving ? (a.kb == 2 ? adj_step_kernel2_moving : adj_step_kernel1_moving)
+                         : (a.kb == 2 ? adj_step_kernel2 : adj_step_kernel1);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out, a.lq_out, a.rad_i,
+                       a.rad_h, a.ang, a);
+}
+
+// Moving source: sum one launch's per-wave slots ([n_slots][nval], nval =
+// 6 kb) in a fixed order and store the sums of every entry: value v of a
+// slot belongs to stage k = v / 6, location loc = (v / 3) % 2 (0: the
+// predictor's half points, 1: the corrector's integer points), sum q = v % 3;
+// stage k reverses forward step top - 1 - k, whose table entry at loc is
+// e = 2 (top - 1 - k) + loc, stored at out[3 e + q].
+__global__ __launch_bounds__(256) void moving_slot_sum_kernel(const double* __restrict__ slots, int64_t n_slots,
+                                                               int nval, int64_t top, double* __restrict__ out) {
+    __shared__ double part[6 * KB_MAX][256];
+    const int t = threadIdx.x;
+    double acc[6 * KB_MAX];
+#pragma unroll
+    for (int v = 0; v < 6 * KB_MAX; ++v) acc[v] = 0.0;
+    for (int64_t i = t; i < n_slots; i += 256)
+#pragma unroll
+        for (int v = 0; v < 6 * KB_MAX; ++v)
+            if (v < nval) acc[v] += slots[i * nval + v];
+#pragma unroll
+    for (int v = 0; v < 6 * KB_MAX; ++v) part[v][t] = acc[v];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int v = 0; v < nval; ++v) part[v][t] += part[v][t + w];
+        __syncthreads();
+    }
+    if (t < nval) {
+        const int k = t / 6, loc = (t / 3) % 2, q = t % 3;
+        out[3 * (2 * (top - 1 - k) + loc) + q] = part[t][0];
+    }
+}
+void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_t top, double* out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(moving_slot_sum_kernel, dim3(1), dim3(256), 0, s, slots, n_slots, 6 * kb, top, out);
 }
 
 // lambda^N = E^H g^N on a zeroed state: (1 - alpha) g_j at column iobs and

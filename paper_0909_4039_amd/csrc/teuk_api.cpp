@@ -240,9 +240,12 @@ int64_t adjoint_slots_used(const teuk_ctx* c) {
 int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
 
 // Workspace layout: [lambda Phi][lambda Pi] (complex128 [nth][nr] each),
-// then the per-wave gradient slots, then 4 doubles of result.
+// then the per-wave gradient slots (3 sums per wave for the static source,
+// 3 per table entry of a launch for a moving one), then 4 doubles of
+// result, then, with an orbit table of n entries, the moving source's
+// per-entry sums [n][3].
 struct AdjLayout {
-    int64_t lam, slots, result, total, n_slots;
+    int64_t lam, slots, result, mout, total, n_slots;
 };
 AdjLayout adjoint_layout(const teuk_ctx* c) {
     AdjLayout L;
@@ -250,8 +253,9 @@ AdjLayout adjoint_layout(const teuk_ctx* c) {
     L.n_slots = adjoint_slots_max(c->geo);
     L.lam = 0;
     L.slots = round256(2 * n * 16);
-    L.result = L.slots + round256(L.n_slots * 3 * 8);
-    L.total = L.result + 256;
+    L.result = L.slots + round256(L.n_slots * 6 * KB_MAX * 8);
+    L.mout = L.result + 256;
+    L.total = L.mout + round256(c->traj_n * 3 * 8);
     return L;
 }
 
@@ -282,7 +286,9 @@ AdjArgs adjoint_args(const teuk_ctx* c, const double* g, int iobs, double alpha,
 
 // The per-launch part: kb reverse steps reading lambda^top, stage times and
 // source phases of the forward steps top-1 .. top-kb; the dL/dw rows are
-// injected when `inject` is set.
+// injected when `inject` is set.  With a.moving the source follows the
+// orbit table from its first entry (forward step k used entries 2k and
+// 2k + 1): r*0 and the phase come from the table, as in the forward step.
 void adjoint_launch_args(const teuk_ctx* c, AdjArgs& a, int kb, int64_t top, double t_start, bool inject) {
     const Geometry& geo = c->geo;
     a.kb = kb;
@@ -290,7 +296,15 @@ void adjoint_launch_args(const teuk_ctx* c, AdjArgs& a, int kb, int64_t top, dou
     for (int k = 0; k < KB_MAX; ++k) {
         const int64_t step = top - 1 - k;   // forward step reversed by stage k
         const double t0 = t_start + double(step) * c->dt, t1 = t0 + 0.5 * c->dt;
-        const double w0 = geo.m * c->Omega * t0, w1 = geo.m * c->Omega * t1;
+        double w0 = geo.m * c->Omega * t0, w1 = geo.m * c->Omega * t1;
+        if (a.moving) {
+            const int64_t e = std::min<int64_t>(std::max<int64_t>(2 * step, 0), c->traj_n - 2);   // k >= kb: unused
+            const double* ent = &c->traj[2 * e];
+            a.rs0[2 * k] = rstar_of_delta(ent[0] - geo.rp, geo.a, geo.M);
+            a.rs0[2 * k + 1] = rstar_of_delta(ent[2] - geo.rp, geo.a, geo.M);
+            w0 = geo.m * ent[1];
+            w1 = geo.m * ent[3];
+        }
         a.t[2 * k] = t0;
         a.t[2 * k + 1] = t1;
         a.ph[2 * k][0] = std::cos(w0);
@@ -301,8 +315,13 @@ void adjoint_launch_args(const teuk_ctx* c, AdjArgs& a, int kb, int64_t top, dou
     }
 }
 
+// The reverse sweep.  Static source: res_host gets the three sums
+// (sum Re c, sum Re c x, sum t Im c).  Moving source (moving_host != NULL):
+// moving_host gets [2n][3], the sums (Re c, Re c x, Im c) of every table
+// entry the n forward steps used.
 int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t n, double t_start, char* ws,
-                  double* dphi0, double* dpi0, double* res_host) {
+                  double* dphi0, double* dpi0, double* res_host, double* moving_host = nullptr) {
+    const bool moving = moving_host != nullptr;
     const Geometry& geo = c->geo;
     const AdjLayout lay = adjoint_layout(c);
     const int64_t npts = geo.nr * geo.nth;
@@ -310,6 +329,7 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
     double* wl[2] = {(double*)(ws + lay.lam), (double*)(ws + lay.lam) + 2 * npts};
     double* slots = (double*)(ws + lay.slots);
     double* result = (double*)(ws + lay.result);
+    double* mout = (double*)(ws + lay.mout);
     // launches from the top: kb steps each, the odd remainder last
     std::vector<int> plan;
     for (int64_t r = n; r > 0;) {
@@ -322,9 +342,20 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
     int cur = (plan.size() % 2 == 1) ? 1 : 0;
     launch_adjoint_init(pair[cur][0], pair[cur][1], g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
     HIP_TRY(c, hipGetLastError());
-    launch_fill_zero(slots, n_slots * 3, c->stream);
-    HIP_TRY(c, hipGetLastError());
+    if (!moving) {
+        launch_fill_zero(slots, n_slots * 3, c->stream);
+        HIP_TRY(c, hipGetLastError());
+    }
     AdjArgs a = adjoint_args(c, g, iobs, alpha, slots);
+    if (moving) {
+        const double sr = c->sig_r * geo.dr;
+        a.moving = 1;
+        a.mslots = slots;
+        a.inv_sr2 = 1.0 / (sr * sr);
+        a.two_sr2 = 2.0 * sr * sr;
+        a.rmin = geo.rmin;
+        a.dr = geo.dr;
+    }
     int64_t top = n;   // this launch reads lambda^top
     for (int kb : plan) {
         adjoint_launch_args(c, a, kb, top, t_start, true);
@@ -334,8 +365,20 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
         a.lq_out = pair[1 - cur][1];
         launch_adjoint_step(a, c->stream);
         HIP_TRY(c, hipGetLastError());
+        if (moving) {
+            // this launch's own grid: a one-step remainder has fewer blocks
+            const int64_t launch_slots = (int64_t)((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks * WG_WAVES;
+            launch_moving_slot_sum(slots, launch_slots, kb, top, mout, c->stream);
+            HIP_TRY(c, hipGetLastError());
+        }
         cur = 1 - cur;
         top -= kb;
+    }
+    if (moving) {
+        HIP_TRY(c, hipMemcpyAsync(moving_host, mout, (size_t)(2 * n * 3) * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return TEUK_OK;
     }
     launch_slot_sum(slots, n_slots, result, c->stream);
     HIP_TRY(c, hipGetLastError());
@@ -593,7 +636,9 @@ int teuk_set_time(teuk_ctx* c, double t, int64_t step) {
     if (!c || !std::isfinite(t)) return TEUK_EINVAL;
     c->t0 = t;
     c->step0 = step;
+    // the observer rows and the orbit table stay attached to the same steps
     c->obs_step0 += step - c->step;
+    c->traj_step0 += step - c->step;
     c->step = step;
     return TEUK_OK;
 }
@@ -766,15 +811,12 @@ int64_t teuk_adjoint_workspace_bytes(teuk_ctx* c) {
     return adjoint_layout(c).total;
 }
 
-static int teuk_adjoint_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
-                 void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
-                 double* dL_damp) {
-    if (!c) return TEUK_EINVAL;
+// Checks shared by both reverse-sweep entry points; finds the observer.
+static int adjoint_check(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, void* workspace,
+                         int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, int* iobs, double* alpha) {
     if (c->status != TEUK_OK) return c->status;
     if (c->prec != TEUK_FP64) return fail(c, TEUK_ENOTSUP, "the reverse sweep is FP64 only");
-    if (c->traj_n > 0) return fail(c, TEUK_ENOTSUP, "the reverse sweep needs a fixed orbit (no trajectory)");
     if (n_steps < 0) return fail(c, TEUK_EINVAL, "negative step count");
-    if (!std::isfinite(t_start)) return fail(c, TEUK_EINVAL, "non-finite t_start");
     if (!dL_dwave || !workspace || !dL_dphi0 || !dL_dpi0) return fail(c, TEUK_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % 256 != 0) return fail(c, TEUK_EINVAL, "workspace not 256-byte aligned");
     if ((uintptr_t)dL_dwave % 16 != 0 || (uintptr_t)dL_dphi0 % 16 != 0 || (uintptr_t)dL_dpi0 % 16 != 0)
@@ -792,13 +834,26 @@ static int teuk_adjoint_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave
     if (overlap(workspace, lay.total, dL_dphi0, nb / 2) || overlap(workspace, lay.total, dL_dpi0, nb / 2) ||
         overlap(dL_dphi0, nb / 2, dL_dpi0, nb / 2))
         return fail(c, TEUK_EINVAL, "workspace and output buffers overlap");
+    if (!observer_index(g, rstar_obs, *iobs, *alpha))
+        return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
+    return TEUK_OK;
+}
+
+static int teuk_adjoint_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+                 void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
+                 double* dL_damp) {
+    if (!c) return TEUK_EINVAL;
+    if (c->traj_n > 0) return fail(c, TEUK_ENOTSUP, "a moving source's reverse sweep is teuk_adjoint_moving");
+    if (!std::isfinite(t_start)) return fail(c, TEUK_EINVAL, "non-finite t_start");
     int iobs;
     double alpha;
-    if (!observer_index(g, rstar_obs, iobs, alpha))
-        return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
+    int rc = adjoint_check(c, rstar_obs, dL_dwave, n_steps, workspace, workspace_bytes, dL_dphi0, dL_dpi0, &iobs,
+                           &alpha);
+    if (rc != TEUK_OK) return rc;
+    const Geometry& g = c->geo;
     double res[3] = {0.0, 0.0, 0.0};
-    int rc = adjoint_sweep(c, iobs, alpha, (const double*)dL_dwave, n_steps, t_start, (char*)workspace,
-                           (double*)dL_dphi0, (double*)dL_dpi0, res);
+    rc = adjoint_sweep(c, iobs, alpha, (const double*)dL_dwave, n_steps, t_start, (char*)workspace,
+                       (double*)dL_dphi0, (double*)dL_dpi0, res);
     if (rc != TEUK_OK) return rc;
     // dT/damp = G e^{-i m Omega t};
     // dT/dr0 = amp G e^{-i m Omega t} [x dr*0/dr0 - i m t dOmega/dr0],
@@ -815,6 +870,51 @@ static int teuk_adjoint_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave
     if (dL_damp) *dL_damp = damp;
     if (dL_dr0) *dL_dr0 = dr0;
     return TEUK_OK;
+}
+
+static int teuk_adjoint_moving_impl(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps,
+                                    void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0,
+                                    double* dL_dtraj, double* dL_damp) {
+    if (!c) return TEUK_EINVAL;
+    if (c->traj_n == 0) return fail(c, TEUK_ESTATE, "no orbit table: teuk_set_trajectory comes first");
+    if (n_steps > 0 && !dL_dtraj) return fail(c, TEUK_EINVAL, "NULL dL_dtraj");
+    if (2 * n_steps > c->traj_n)
+        return fail(c, TEUK_EINVAL, "%lld steps need %lld orbit entries, the table has %lld", (long long)n_steps,
+                    (long long)(2 * n_steps), (long long)c->traj_n);
+    int iobs;
+    double alpha;
+    int rc = adjoint_check(c, rstar_obs, dL_dwave, n_steps, workspace, workspace_bytes, dL_dphi0, dL_dpi0, &iobs,
+                           &alpha);
+    if (rc != TEUK_OK) return rc;
+    std::vector<double> sums((size_t)(2 * n_steps * 3) + 3);
+    rc = adjoint_sweep(c, iobs, alpha, (const double*)dL_dwave, n_steps, 0.0, (char*)workspace,
+                       (double*)dL_dphi0, (double*)dL_dpi0, nullptr, sums.data());
+    if (rc != TEUK_OK) return rc;
+    // per entry e, with c = conj(a_T) U (U: unit-amplitude source):
+    // dL/dr0_e = amp dr*/dr(r0_e) sum Re c x, dL/dphi_e = amp m sum Im c,
+    // dL/damp = sum over entries of sum Re c (summed here in entry order)
+    const Geometry& g = c->geo;
+    double damp = 0.0;
+    for (int64_t e = 0; e < 2 * n_steps; ++e) {
+        const double r0 = c->traj[2 * e];
+        const double drs0 = (r0 * r0 + g.a * g.a) / (r0 * r0 - 2.0 * g.M * r0 + g.a * g.a);
+        const double* v = &sums[3 * e];
+        damp += v[0];
+        dL_dtraj[2 * e] = c->amp * drs0 * v[1];
+        dL_dtraj[2 * e + 1] = c->amp * double(g.m) * v[2];
+    }
+    if (dL_damp) *dL_damp = damp;
+    return TEUK_OK;
+}
+
+int teuk_adjoint_moving(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, void* workspace,
+                        int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dtraj, double* dL_damp) {
+    try {
+        return teuk_adjoint_moving_impl(c, rstar_obs, dL_dwave, n_steps, workspace, workspace_bytes, dL_dphi0,
+                                        dL_dpi0, dL_dtraj, dL_damp);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation failed");
+    }
 }
 
 int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,

@@ -138,6 +138,14 @@ struct AdjArgs {
     int32_t iobs;
     double alpha;
     double* slots;        // [blocks][WG_WAVES][3] source-gradient partial sums
+    // moving source: r*0 of the orbit-table entry of every stage, [2k] for
+    // step k's predictor (half points) and [2k + 1] for its corrector
+    // (integer points); per-launch partial sums go to mslots,
+    // [blocks][WG_WAVES][2 kb][3], written (not added) by every wave
+    int32_t moving;
+    double rs0[2 * KB_MAX];
+    double inv_sr2, two_sr2, rmin, dr;
+    double* mslots;
 };
 
 // One instance of a batch (FP64): its bound buffers, tables and constants.
@@ -194,6 +202,8 @@ void launch_adjoint_init(double* lp, double* lq, const double* g_row, int64_t n,
                          hipStream_t s);
 void launch_fill_zero(double* x, int64_t n, hipStream_t s);
 void launch_slot_sum(const double* slots, int64_t n_slots, double* out, hipStream_t s);
+void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_t top, double* out,
+                            hipStream_t s);
 void launch_count_nonfinite_fp64(const double* x, int64_t n, unsigned int* flag, hipStream_t s);
 void launch_count_nonfinite_fp32(const float* x, int64_t n, unsigned int* flag, hipStream_t s);
 

@@ -57,6 +57,7 @@ class Solver:
             check(_lib.lib().teuk_bind_state(self._ctx, *[b.data_ptr() for b in self._bufs]), self._ctx)
         self.wave = None
         self.source = None
+        self.trajectory = None
 
     # ------------------------------------------------------------ state
     def _cur(self):
@@ -87,6 +88,7 @@ class Solver:
         """Moving source: r0_phase[k] = (r0, phi) at t_now + k dt/2 (numpy (n, 2)); None: fixed orbit."""
         if r0_phase is None:
             check(_lib.lib().teuk_set_trajectory(self._ctx, None, 0), self._ctx)
+            self.trajectory = None
             return
         import numpy as np
         tab = np.ascontiguousarray(r0_phase, dtype=np.float64)
@@ -94,6 +96,7 @@ class Solver:
             raise ValueError("r0_phase must have shape (n, 2)")
         check(_lib.lib().teuk_set_trajectory(self._ctx, tab.ctypes.data_as(ctypes.c_void_p), tab.shape[0]),
               self._ctx)
+        self.trajectory = tab
 
     def set_observer(self, rstar_obs, capacity_rows):
         """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
@@ -201,6 +204,33 @@ class Solver:
                                           dphi.data_ptr(), dpi.data_ptr(), ctypes.byref(dr0), ctypes.byref(damp)),
                   self._ctx)
         return dphi, dpi, dr0.value, damp.value
+
+    def adjoint_moving(self, dL_dwave, n_steps, rstar_obs):
+        """Reverse sweep for the orbit table of ``set_trajectory`` (FP64), the
+        forward run having started at its first entry.  Returns (dL/dPhi0,
+        dL/dPi0, dL/dtraj, dL/damp) with dL/dtraj a float64 numpy array
+        (2 n_steps, 2): row e = (dL/dr0_e, dL/dphi_e)."""
+        import numpy as np
+        n = int(n_steps)
+        g = torch.as_tensor(dL_dwave).to(self.device, torch.complex128).contiguous()
+        if g.shape != (n + 1, self.shape[0]):
+            raise ValueError(f"dL_dwave has shape {tuple(g.shape)}, expected {(n + 1, self.shape[0])}")
+        nbytes = self.adjoint_workspace_bytes()
+        ws = torch.empty((nbytes + 255) // 8 + 32, dtype=torch.float64, device=self.device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        dphi = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        dpi = torch.empty(self.shape, dtype=torch.complex128, device=self.device)
+        dtraj = np.zeros((max(2 * n, 1), 2), dtype=np.float64)
+        damp = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            check(_lib.lib().teuk_adjoint_moving(self._ctx, float(rstar_obs), g.data_ptr(), n,
+                                                 ctypes.c_void_p(base + off), int(ws.numel() * 8 - off),
+                                                 dphi.data_ptr(), dpi.data_ptr(),
+                                                 dtraj.ctypes.data_as(ctypes.c_void_p), ctypes.byref(damp)),
+                  self._ctx)
+        return dphi, dpi, dtraj[:2 * n], damp.value
 
     def check_finite(self):
         """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""

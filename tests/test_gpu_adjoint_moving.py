@@ -1,0 +1,207 @@
+"""GPU reverse sweep for a moving (inspiralling) source, teuk_adjoint_moving
+through the C ABI: gradients with respect to every orbit-table entry
+(r0_e, phi_e), the amplitude and the initial data.
+
+Bars: against the oracle's moving-source sweep, FP64 relative L2 <= 1e-12
+for dL/du^0 and <= 1e-11 for dL/dtraj and dL/damp; dL/du^0 equal bit for
+bit to the static sweep's (it does not depend on the source); across
+tilings, dL/du^0 bitwise and dL/dtraj to 1e-13; on the adjoint workload's
+full 4096 x 256 grid, a fixed orbit chains back to the static dL/dr0 and an
+inspiral matches central differences of GPU forward runs.
+"""
+import numpy as np
+import pytest
+
+from paper_0909_4039_amd import inputs, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = [
+    # nr, nth, rmin, rmax, a, m, s, r_start, q, amp, robs, n
+    dict(name="pin_48x10", nr=48, nth=10, rmin=-12.0, rmax=24.0, a=0.6, m=2, s=-2, r0=7.0, q=0.3, amp=1.0,
+         robs=6.3, n=16),
+    dict(name="strips_150x24", nr=150, nth=24, rmin=-20.0, rmax=55.0, a=0.6, m=2, s=-2, r0=10.0, q=0.05,
+         amp=1.0, robs=14.0, n=40),
+    dict(name="odd_n_257x33_m3", nr=257, nth=33, rmin=-50.0, rmax=100.0, a=0.9, m=3, s=-2, r0=8.0, q=0.2,
+         amp=0.7, robs=12.0, n=31),
+    dict(name="kerr_130x70_m-2", nr=130, nth=70, rmin=-30.0, rmax=60.0, a=0.99, m=-2, s=-2, r0=6.0, q=0.5,
+         amp=1.0, robs=8.0, n=25),
+]
+
+
+def _dt(oracle_mod, c):
+    return oracle_mod.stable_dt(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], 1.0, c["m"], c["s"], 10000)
+
+
+def _traj(c, dt, n):
+    return inputs.inspiral_trajectory(c["r0"], c["a"], 1.0, c["q"], dt, n)
+
+
+def _g(c, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n + 1, c["nth"])) + 1j * rng.standard_normal((n + 1, c["nth"]))
+
+
+def _solver(c, dt, traj=None):
+    from paper_0909_4039_amd.solver import Solver
+    s = Solver(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], 1.0, c["m"], c["s"], dt)
+    s.set_source(c["r0"], c["amp"])
+    if traj is not None:
+        s.set_trajectory(traj)
+    return s
+
+
+def _gpu(c, dt, traj, g, n, rows=0, kb=1):
+    s = _solver(c, dt, traj)
+    s.set_adjoint_tiling(rows, kb)
+    dphi, dpi, dtraj, damp = s.adjoint_moving(g, n, c["robs"])
+    out = (dphi.cpu().numpy(), dpi.cpu().numpy(), dtraj, damp)
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("kb", [1, 2])
+@pytest.mark.parametrize("c", CASES, ids=[c["name"] for c in CASES])
+def test_moving_adjoint_parity(oracle_mod, c, kb):
+    dt = _dt(oracle_mod, c)
+    n = c["n"]
+    traj = _traj(c, dt, n)
+    g = _g(c, n, seed=81)
+    print(f"[gpu] moving adjoint parity {c['name']} n={n} kb={kb}", flush=True)
+    gp, gq, gt, ga = _gpu(c, dt, traj, g, n, kb=kb)
+    o = oracle_mod.Oracle(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], 1.0, c["m"], c["s"], dt, r0=c["r0"],
+                          amp=c["amp"], rstar_obs=c["robs"])
+    o.set_trajectory(traj)
+    op, oq, ot, oa = o.adjoint_run_moving(g, n)
+    assert np.linalg.norm(ot[:, 0]) > 0 and np.linalg.norm(ot[:, 1]) > 0
+    assert rel(gp, op) <= 1e-12 and rel(gq, oq) <= 1e-12, (rel(gp, op), rel(gq, oq))
+    assert rel(gt[:, 0], ot[:, 0]) <= 1e-11 and rel(gt[:, 1], ot[:, 1]) <= 1e-11, \
+        (rel(gt[:, 0], ot[:, 0]), rel(gt[:, 1], ot[:, 1]))
+    assert abs(ga - oa) <= 1e-11 * abs(oa)
+
+
+def test_moving_adjoint_tilings_and_static_lambda(oracle_mod):
+    c = CASES[2]
+    dt = _dt(oracle_mod, c)
+    n = c["n"]
+    traj = _traj(c, dt, n)
+    g = _g(c, n, seed=82)
+    print("[gpu] moving adjoint: tilings and the static sweep's lambda", flush=True)
+    ref = _gpu(c, dt, traj, g, n, rows=1, kb=1)
+    for rows, kb in ((5, 1), (7, 2), (64, 2), (0, 2), (4096, 1)):
+        got = _gpu(c, dt, traj, g, n, rows=rows, kb=kb)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (rows, kb)
+        scale = np.abs(ref[2]).max(axis=0)
+        assert np.all(np.abs(got[2] - ref[2]) <= 1e-13 * scale), (rows, kb)
+        assert abs(got[3] - ref[3]) <= 1e-13 * abs(ref[3])
+    # repeated calls give the same bits
+    again = _gpu(c, dt, traj, g, n, rows=1, kb=1)
+    assert all(np.array_equal(x, y) for x, y in zip(again[:3], ref[:3])) and again[3] == ref[3]
+    # dL/du^0 does not depend on the source: the static sweep's, bit for bit
+    s = _solver(c, dt)
+    sp, sq, _, _ = s.adjoint(g, n, c["robs"])
+    assert np.array_equal(sp.cpu().numpy(), ref[0]) and np.array_equal(sq.cpu().numpy(), ref[1])
+    s.close()
+
+
+def test_moving_adjoint_errors(oracle_mod):
+    from paper_0909_4039_amd import TeukError
+    c = CASES[0]
+    dt = _dt(oracle_mod, c)
+    n = 6
+    g = _g(c, n, seed=83)
+    s = _solver(c, dt)
+    with pytest.raises(TeukError) as e:          # no orbit table
+        s.adjoint_moving(g, n, c["robs"])
+    assert e.value.code == -2
+    s.set_trajectory(_traj(c, dt, n)[: 2 * n - 1])
+    with pytest.raises(TeukError) as e:          # table shorter than 2n entries
+        s.adjoint_moving(g, n, c["robs"])
+    assert e.value.code == -1
+    s.set_trajectory(_traj(c, dt, n))
+    with pytest.raises(TeukError) as e:          # the static sweep refuses a moving source
+        s.adjoint(g, n, c["robs"])
+    assert e.value.code == -5
+    dphi, dpi, dtraj, damp = s.adjoint_moving(g[:1], 0, c["robs"])
+    assert dtraj.shape == (0, 2) and damp == 0.0
+    s.close()
+
+
+W = workloads.ADJOINT
+
+
+def _full():
+    from paper_0909_4039_amd.solver import suggest_dt
+    c = dict(nr=W.nr, nth=W.nth, rmin=W.rstar_min, rmax=W.rstar_max, a=W.a, m=W.m, s=W.s, r0=W.r0, amp=W.amp,
+             robs=14.0)
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, 1.0, W.m, W.s, W.steps)
+    return c, dt
+
+
+def test_fixed_orbit_chains_to_static_full_grid_4096x256():
+    # phi_e = Omega t_e, r0_e = r0: sum_e dL/dr0_e + dL/dphi_e t_e dOmega/dr0
+    # is the static sweep's dL/dr0.  The observer sits at r* = 14, next to the
+    # source (r* = 12.8), so 2000 steps carry the source into the waveform.
+    c, dt = _full()
+    n = 2000
+    g = _g(c, n, seed=84)
+    print(f"[gpu] moving adjoint, fixed orbit, 4096x256 n={n}", flush=True)
+    s = _solver(c, dt)
+    sp, sq, s_r0, s_amp = s.adjoint(g, n, c["robs"])
+    s.set_trajectory(inputs.inspiral_trajectory(c["r0"], c["a"], 1.0, 0.0, dt, n))
+    mp, mq, dtraj, m_amp = s.adjoint_moving(g, n, c["robs"])
+    assert np.array_equal(mp.cpu().numpy(), sp.cpu().numpy()) and np.array_equal(mq.cpu().numpy(), sq.cpu().numpy())
+    t = np.arange(2 * n) * 0.5 * dt
+    r0, a = c["r0"], c["a"]
+    dOm = -1.5 * np.sqrt(r0) / (r0 ** 1.5 + a) ** 2
+    chained = np.sum(dtraj[:, 0]) + np.sum(dtraj[:, 1] * t) * dOm
+    print(f"[gpu] static dL/dr0 {s_r0:.15e} chained {chained:.15e}", flush=True)
+    assert s_r0 != 0.0
+    assert chained == pytest.approx(s_r0, rel=1e-10)
+    assert m_amp == pytest.approx(s_amp, rel=1e-12)
+    s.close()
+
+
+def test_inspiral_central_differences_full_grid_4096x256():
+    # an EMRI-like inspiral (mass ratio 1e-4) over 2000 steps; L = Re sum
+    # conj(G) w, so dL/dw = G; dL/dr0_e and dL/dphi_e of a few entries
+    # against central differences of GPU forward runs
+    import torch
+    c, dt = _full()
+    n = 2000
+    traj = inputs.inspiral_trajectory(c["r0"], c["a"], 1.0, 1e-4, dt, n)
+    g = _g(c, n, seed=85)
+    s = _solver(c, dt, traj)
+    phi, pi = inputs.smooth_random_state(W.nr, W.nth, W.rstar_min, W.rstar_max, seed=86)
+
+    def loss(tab):
+        s.set_trajectory(tab)
+        s.set_state(phi, pi)
+        s.set_time(0.0, 0)
+        s.set_observer(c["robs"], n + 1)
+        s.step(n)
+        torch.cuda.synchronize()
+        return float(np.sum((np.conj(g) * s.wave.cpu().numpy()).real))
+
+    print(f"[gpu] moving adjoint FD, 4096x256 n={n}", flush=True)
+    s.set_trajectory(traj)
+    _, _, dtraj, _ = s.adjoint_moving(g, n, c["robs"])
+    scale = np.abs(dtraj).max(axis=0)
+    assert np.all(scale > 0)
+    h = 1e-5
+    for e in (0, 1, 601, 1200):
+        for k in (0, 1):
+            tp, tm = traj.copy(), traj.copy()
+            tp[e, k] += h
+            tm[e, k] -= h
+            fd = (loss(tp) - loss(tm)) / (2 * h)
+            print(f"[gpu] entry {e} {'r0' if k == 0 else 'phi'}: adjoint {dtraj[e, k]:.12e} fd {fd:.12e}",
+                  flush=True)
+            assert abs(fd - dtraj[e, k]) <= 1e-6 * scale[k]
+    s.close()
