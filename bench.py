@@ -93,7 +93,9 @@ def time_adjoint(steps=None):
     """Adjoint workload (a = 0.6, m = 2, 4096 x 256, 20000 steps, source r0 = 10,
     observer r* = 300): wall time of the forward run with the waveform
     recorded, and of the reverse sweep that returns dL/dPhi0, dL/dPi0,
-    dL/dr0 and dL/damp for L = sum |w|^2 (no forward state kept)."""
+    dL/dr0 and dL/damp for L = sum |w|^2 (no forward state kept); then the
+    same for an inspiralling source, whose sweep returns the gradient of
+    every orbit-table entry."""
     import torch
     from paper_0909_4039_amd import inputs, workloads
     from paper_0909_4039_amd.solver import Solver, suggest_dt
@@ -109,9 +111,13 @@ def time_adjoint(steps=None):
     tuned = s.autotune(10)
     adj_tuned = s.adjoint_autotune(10)
 
+    table = None
+
     def forward():
         s.set_state(phi, pi)
         s.set_time(0.0, 0)
+        if table is not None:
+            s.set_trajectory(table)   # the run starts at the table's first entry
         s.set_observer(W.rstar_obs, n + 1)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -129,11 +135,27 @@ def time_adjoint(steps=None):
         t = time.perf_counter()
         s.adjoint(g, n, W.rstar_obs)
         adj.append(time.perf_counter() - t)
+    # the same grid and run with an inspiralling source (mass ratio 1e-4):
+    # forward with the orbit table, and the reverse sweep that also returns
+    # dL/dr0 and dL/dphi of every table entry
+    table = inputs.inspiral_trajectory(W.r0, W.a, W.M, 1e-4, dt, n)
+    forward()
+    fwd_m = min(forward() for _ in range(3))
+    g = (2.0 * s.wave).contiguous()
+    s.adjoint_moving(g, n, W.rstar_obs)
+    adj_m = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.adjoint_moving(g, n, W.rstar_obs)
+        adj_m.append(time.perf_counter() - t)
     s.close()
     return {"workload": W.name, "steps": n, "forward_ms": fwd * 1e3, "adjoint_ms": min(adj) * 1e3,
             "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0,
             "rows_per_wave": tuned[0], "steps_per_launch": tuned[1],
-            "adjoint_rows_per_wave": adj_tuned[0], "adjoint_steps_per_launch": adj_tuned[1]}
+            "adjoint_rows_per_wave": adj_tuned[0], "adjoint_steps_per_launch": adj_tuned[1],
+            "inspiral": {"forward_ms": fwd_m * 1e3, "adjoint_ms": min(adj_m) * 1e3,
+                         "adjoint_over_forward": min(adj_m) / fwd_m, "gradient_entries": 2 * n}}
 
 
 def _pulse(w):

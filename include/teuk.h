@@ -95,8 +95,10 @@ int teuk_set_source(teuk_ctx* ctx, double r0, double amp, double sigma_r_cells,
  * t^n + dt/2 (corrector); teuk_step fails with TEUK_EINVAL past the table.
  * With r0 fixed and phi = Omega t it is the fixed-orbit source up to
  * rounding.  r0_phase = NULL returns to the fixed orbit.  Requires
- * teuk_set_source first (TEUK_ESTATE) and r0 > r+ in every entry.  Its
- * reverse sweep is teuk_adjoint_moving. */
+ * teuk_set_source first (TEUK_ESTATE) and r0 > r+ in every entry.
+ * teuk_set_time relabels steps without moving the table; to run again from
+ * the table's first entry, set it again.  Its reverse sweep is
+ * teuk_adjoint_moving. */
 int teuk_set_trajectory(teuk_ctx* ctx, const double* r0_phase, int64_t n_half);
 
 /* Waveform recorder: from now on each step records

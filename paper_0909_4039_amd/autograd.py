@@ -15,6 +15,12 @@ states plus one recomputed forward sweep) is replaced by zero stored states
 and no recomputation, and the backward costs one sweep of the same size as
 the forward.
 
+``waveform_moving(solver, phi0, pi0, traj, amp, n_steps, rstar_obs)`` does
+the same for a moving source that follows an orbit table (r0, phi) at
+every half step (an inspiral, the paper's Fig. 1).  Its backward pass
+(``teuk_adjoint_moving``) returns the gradient for every table row, so a
+differentiable orbit law chains through it.
+
 Gradient convention: torch's for complex tensors (for L = |z|^2 the
 gradient is 2z), which is dL/dRe + i dL/dIm, the library's convention.
 """
@@ -31,6 +37,7 @@ class TeukWaveform(torch.autograd.Function):
         sig = solver.source[2:] if solver.source is not None else (2.0, 2.0)
         r0f, ampf = float(r0), float(amp)
         solver.set_source(r0f, ampf, *sig)
+        solver.set_trajectory(None)   # a fixed orbit
         solver.set_state(phi0.detach(), pi0.detach())
         solver.set_time(float(t_start), 0)
         wave = solver.set_observer(rstar_obs, int(n_steps) + 1)
@@ -52,6 +59,7 @@ class TeukWaveform(torch.autograd.Function):
         r0f, ampf, sig, n, robs, t0 = ctx.args
         # the solver may have been used in between: restore this call's source
         solver.set_source(r0f, ampf, *sig)
+        solver.set_trajectory(None)
         dphi, dpi, dr0, damp = solver.adjoint(g, n, robs, t0)
         return (dphi, dpi, torch.tensor(dr0, dtype=ctx.r0_meta[0], device=ctx.r0_meta[1]),
                 torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]), None, None, None, None)
@@ -60,3 +68,57 @@ class TeukWaveform(torch.autograd.Function):
 def waveform(solver, phi0, pi0, r0, amp, n_steps, rstar_obs, t_start=0.0):
     """Differentiable waveform w^0..w^n (see the module docstring)."""
     return TeukWaveform.apply(phi0, pi0, r0, amp, solver, n_steps, rstar_obs, t_start)
+
+
+class TeukWaveformMoving(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, pi0, traj, amp, solver, n_steps, rstar_obs):
+        if solver.prec != 64:
+            raise ValueError("the differentiable waveform needs an FP64 solver")
+        import numpy as np
+        sig = solver.source[2:] if solver.source is not None else (2.0, 2.0)
+        tab = np.ascontiguousarray(traj.detach().to("cpu", torch.float64).numpy())
+        ampf = float(amp)
+        n = int(n_steps)
+        # a source must be set before the table; its radius is overridden by the table
+        solver.set_source(float(tab[0, 0]), ampf, *sig)
+        solver.set_state(phi0.detach(), pi0.detach())
+        solver.set_time(0.0, 0)
+        solver.set_trajectory(tab)
+        wave = solver.set_observer(rstar_obs, n + 1)
+        solver.step(n)
+        cur = torch.cuda.current_stream(solver.device)
+        cur.wait_stream(solver.stream)
+        out = wave.clone()
+        wave.record_stream(cur)
+        solver.clear_observer()
+        ctx.solver = solver
+        ctx.args = (tab, ampf, sig, n, float(rstar_obs))
+        ctx.traj_meta = (traj.dtype, traj.device, tuple(traj.shape))
+        ctx.amp_meta = (amp.dtype, amp.device) if torch.is_tensor(amp) else (torch.float64, phi0.device)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        solver = ctx.solver
+        tab, ampf, sig, n, robs = ctx.args
+        # the solver may have been used in between: restore this call's source and table
+        solver.set_source(float(tab[0, 0]), ampf, *sig)
+        solver.set_trajectory(tab)
+        dphi, dpi, dtraj, damp = solver.adjoint_moving(g, n, robs)
+        dt, dev, shape = ctx.traj_meta
+        full = torch.zeros(shape, dtype=torch.float64)
+        full[: 2 * n] = torch.from_numpy(dtraj)
+        return (dphi, dpi, full.to(dev, dt), torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]),
+                None, None, None)
+
+
+def waveform_moving(solver, phi0, pi0, traj, amp, n_steps, rstar_obs):
+    """Differentiable waveform w^0..w^n of a moving source.
+
+    ``traj`` is the orbit table (n_half, 2), row k = (r0, phi) at t = k dt/2,
+    n_half >= 2 n_steps; the run starts at t = 0 from (phi0, pi0).  Its
+    gradient is dL/dr0_k, dL/dphi_k per row (rows past 2 n_steps get zero), so
+    any differentiable orbit law that produced the table (a torch function of
+    the initial radius or the mass ratio) chains through autograd."""
+    return TeukWaveformMoving.apply(phi0, pi0, traj, amp, solver, n_steps, rstar_obs)

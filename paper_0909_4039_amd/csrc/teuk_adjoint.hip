@@ -237,6 +237,48 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
     st.yq1 = yQ;
 }
 
+// Moving source: sum one launch's per-wave slots ([n_slots][nval], nval =
+// 6 kb) in a fixed order (thread t takes slots t, t + 256, ... in turn, then
+// a fixed tree) and store the sums of every entry: value v of a slot
+// belongs to stage k = v / 6, location loc = (v / 3) % 2 (0: the
+// predictor's half points, 1: the corrector's integer points), sum q = v % 3;
+// stage k reverses forward step top - 1 - k, whose table entry at loc is
+// e = 2 (top - 1 - k) + loc, stored at out[3 e + q].  Run by one block of
+// 256 threads; part is LDS of 6 KB_MAX x 256 doubles.
+__device__ __forceinline__ void reduce_moving_slots(const double* __restrict__ slots, int64_t n_slots, int nval,
+                                                    int64_t top, double* __restrict__ out, double* part) {
+    const int t = threadIdx.x;
+    constexpr int NV = 6 * KB_MAX, U = 4;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int64_t i0 = t; i0 < n_slots; i0 += 256 * U) {
+        double x[U][NV];   // U slots' loads in flight before the adds
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + 256 * u;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) x[u][v] = (i < n_slots && v < nval) ? slots[i * nval + v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += x[u][v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) part[v * 256 + t] = acc[v];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int v = 0; v < nval; ++v) part[v * 256 + t] += part[v * 256 + t + w];
+        __syncthreads();
+    }
+    if (t < nval) {
+        const int k = t / 6, loc = (t / 3) % 2, q = t % 3;
+        out[3 * (2 * (top - 1 - k) + loc) + q] = part[t * 256];
+    }
+}
+
 template <int KB, bool MOV>
 __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, const double* __restrict__ lq,
                                               double* __restrict__ lp_out, double* __restrict__ lq_out,
@@ -246,19 +288,27 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
+    // moving source: block 0 reduces the previous launch's slots (in the LDS
+    // the tiles use for their tables) while the other blocks run the tiles
+    if (MOV && blockIdx.x == 0) {
+        if (A.prev_mslots != nullptr)
+            reduce_moving_slots(A.prev_mslots, A.prev_n_slots, 6 * A.prev_kb, A.prev_top, A.mout, &srad_all[0][0][0][0]);
+        return;
+    }
+    const int tb = (int)blockIdx.x - (MOV ? 1 : 0);   // tile block
+    const int blk = xcd_remap(tb, (int)gridDim.x - (MOV ? 1 : 0));
     const int chunk = blk / ngrp;
     const int grp = blk - chunk * ngrp;
     const int strip = grp * WG_WAVES + wid;
     if (strip >= A.n_strips) {   // wave-uniform; the kernel has no barriers
         if (MOV && (threadIdx.x & (WAVE - 1)) < 6 * KB)   // this wave's per-launch slot holds zeros
-            A.mslots[((int64_t)blockIdx.x * WG_WAVES + wid) * (6 * KB) + (threadIdx.x & (WAVE - 1))] = 0.0;
+            A.mslots[((int64_t)tb * WG_WAVES + wid) * (6 * KB) + (threadIdx.x & (WAVE - 1))] = 0.0;
         return;
     }
     const int nr = A.nr, nth = A.nth;
     const int c = strip * SO - KB + lane;
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
-    __shared__ double srad_all[WG_WAVES][2][N_RAD_USED][WAVE];
     double (*srad)[N_RAD_USED][WAVE] = srad_all[wid];
     for (int k = 0; k < 2 * N_RAD_USED; ++k) {
         const int loc = k / N_RAD_USED, f = k % N_RAD_USED;
@@ -362,7 +412,7 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     if constexpr (MOV) {
         // wave sums of every entry in a fixed butterfly order, written into
         // this launch's slot of the wave
-        double* slot = A.mslots + ((int64_t)blockIdx.x * WG_WAVES + wid) * (6 * KB);
+        double* slot = A.mslots + ((int64_t)tb * WG_WAVES + wid) * (6 * KB);
 #pragma unroll
         for (int e = 0; e < 2 * KB; ++e) {
             double v[3] = {macc[e].sa, macc[e].sx, macc[e].st};
@@ -383,7 +433,7 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     for (int q = 0; q < 3; ++q)
         for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off, WAVE);
     if (lane == 0) {
-        double* slot = A.slots + ((int64_t)blockIdx.x * WG_WAVES + wid) * 3;
+        double* slot = A.slots + ((int64_t)tb * WG_WAVES + wid) * 3;
         slot[0] += v[0];
         slot[1] += v[1];
         slot[2] += v[2];
@@ -413,42 +463,18 @@ __global__ __launch_bounds__(256) void adj_step_kernel2_moving(ADJ_PARAMS) {
 #undef ADJ_PARAMS
 
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s) {
-    int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
+    int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks + (a.moving ? 1 : 0);
     auto kern = a.moving ? (a.kb == 2 ? adj_step_kernel2_moving : adj_step_kernel1_moving)
                          : (a.kb == 2 ? adj_step_kernel2 : adj_step_kernel1);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.lp, a.lq, a.lp_out, a.lq_out, a.rad_i,
                        a.rad_h, a.ang, a);
 }
 
-// Moving source: sum one launch's per-wave slots ([n_slots][nval], nval =
-// 6 kb) in a fixed order and store the sums of every entry: value v of a
-// slot belongs to stage k = v / 6, location loc = (v / 3) % 2 (0: the
-// predictor's half points, 1: the corrector's integer points), sum q = v % 3;
-// stage k reverses forward step top - 1 - k, whose table entry at loc is
-// e = 2 (top - 1 - k) + loc, stored at out[3 e + q].
+// The last launch's slots (no later launch reduces them).
 __global__ __launch_bounds__(256) void moving_slot_sum_kernel(const double* __restrict__ slots, int64_t n_slots,
                                                                int nval, int64_t top, double* __restrict__ out) {
-    __shared__ double part[6 * KB_MAX][256];
-    const int t = threadIdx.x;
-    double acc[6 * KB_MAX];
-#pragma unroll
-    for (int v = 0; v < 6 * KB_MAX; ++v) acc[v] = 0.0;
-    for (int64_t i = t; i < n_slots; i += 256)
-#pragma unroll
-        for (int v = 0; v < 6 * KB_MAX; ++v)
-            if (v < nval) acc[v] += slots[i * nval + v];
-#pragma unroll
-    for (int v = 0; v < 6 * KB_MAX; ++v) part[v][t] = acc[v];
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w)
-            for (int v = 0; v < nval; ++v) part[v][t] += part[v][t + w];
-        __syncthreads();
-    }
-    if (t < nval) {
-        const int k = t / 6, loc = (t / 3) % 2, q = t % 3;
-        out[3 * (2 * (top - 1 - k) + loc) + q] = part[t][0];
-    }
+    __shared__ double part[6 * KB_MAX * 256];
+    reduce_moving_slots(slots, n_slots, nval, top, out, part);
 }
 void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_t top, double* out,
                             hipStream_t s) {

@@ -240,10 +240,10 @@ int64_t adjoint_slots_used(const teuk_ctx* c) {
 int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
 
 // Workspace layout: [lambda Phi][lambda Pi] (complex128 [nth][nr] each),
-// then the per-wave gradient slots (3 sums per wave for the static source,
-// 3 per table entry of a launch for a moving one), then 4 doubles of
-// result, then, with an orbit table of n entries, the moving source's
-// per-entry sums [n][3].
+// then the per-wave gradient slots (3 sums per wave for the static source;
+// for a moving one, two buffers of 3 per table entry of a launch, used by
+// alternate launches), then 4 doubles of result, then, with an orbit table
+// of n entries, the moving source's per-entry sums [n][3].
 struct AdjLayout {
     int64_t lam, slots, result, mout, total, n_slots;
 };
@@ -253,7 +253,7 @@ AdjLayout adjoint_layout(const teuk_ctx* c) {
     L.n_slots = adjoint_slots_max(c->geo);
     L.lam = 0;
     L.slots = round256(2 * n * 16);
-    L.result = L.slots + round256(L.n_slots * 6 * KB_MAX * 8);
+    L.result = L.slots + 2 * round256(L.n_slots * 6 * KB_MAX * 8);
     L.mout = L.result + 256;
     L.total = L.mout + round256(c->traj_n * 3 * 8);
     return L;
@@ -347,10 +347,12 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
         HIP_TRY(c, hipGetLastError());
     }
     AdjArgs a = adjoint_args(c, g, iobs, alpha, slots);
+    double* mbuf[2] = {slots, slots + lay.n_slots * 6 * KB_MAX};   // alternate launches
+    int64_t launch = 0;
     if (moving) {
         const double sr = c->sig_r * geo.dr;
         a.moving = 1;
-        a.mslots = slots;
+        a.mout = mout;
         a.inv_sr2 = 1.0 / (sr * sr);
         a.two_sr2 = 2.0 * sr * sr;
         a.rmin = geo.rmin;
@@ -358,6 +360,14 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
     }
     int64_t top = n;   // this launch reads lambda^top
     for (int kb : plan) {
+        if (moving) {
+            // the previous launch's slots are reduced by block 0 of this one
+            a.prev_mslots = launch > 0 ? a.mslots : nullptr;
+            a.prev_n_slots = (int64_t)((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks * WG_WAVES;
+            a.prev_kb = a.kb;
+            a.prev_top = top + a.kb;
+            a.mslots = mbuf[launch & 1];
+        }
         adjoint_launch_args(c, a, kb, top, t_start, true);
         a.lp = pair[cur][0];
         a.lq = pair[cur][1];
@@ -365,16 +375,18 @@ int adjoint_sweep(teuk_ctx* c, int iobs, double alpha, const double* g, int64_t 
         a.lq_out = pair[1 - cur][1];
         launch_adjoint_step(a, c->stream);
         HIP_TRY(c, hipGetLastError());
-        if (moving) {
-            // this launch's own grid: a one-step remainder has fewer blocks
-            const int64_t launch_slots = (int64_t)((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks * WG_WAVES;
-            launch_moving_slot_sum(slots, launch_slots, kb, top, mout, c->stream);
-            HIP_TRY(c, hipGetLastError());
-        }
+        ++launch;
         cur = 1 - cur;
         top -= kb;
     }
     if (moving) {
+        if (launch > 0) {
+            // the last launch's slots, over its own grid (a one-step
+            // remainder has fewer blocks); it reversed steps top .. top+kb-1
+            const int64_t last_slots = (int64_t)((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks * WG_WAVES;
+            launch_moving_slot_sum(a.mslots, last_slots, a.kb, top + a.kb, mout, c->stream);
+            HIP_TRY(c, hipGetLastError());
+        }
         HIP_TRY(c, hipMemcpyAsync(moving_host, mout, (size_t)(2 * n * 3) * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));

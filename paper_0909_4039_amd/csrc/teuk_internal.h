@@ -141,11 +141,17 @@ struct AdjArgs {
     // moving source: r*0 of the orbit-table entry of every stage, [2k] for
     // step k's predictor (half points) and [2k + 1] for its corrector
     // (integer points); per-launch partial sums go to mslots,
-    // [blocks][WG_WAVES][2 kb][3], written (not added) by every wave
+    // [tile blocks][WG_WAVES][2 kb][3], written (not added) by every wave.
+    // The launch has one block more than tiles: block 0 reduces the previous
+    // launch's slots (prev_mslots, NULL for the first launch) into mout.
     int32_t moving;
     double rs0[2 * KB_MAX];
     double inv_sr2, two_sr2, rmin, dr;
     double* mslots;
+    const double* prev_mslots;
+    int64_t prev_n_slots, prev_top;
+    int32_t prev_kb;
+    double* mout;         // [table entries][3] per-entry sums
 };
 
 // One instance of a batch (FP64): its bound buffers, tables and constants.

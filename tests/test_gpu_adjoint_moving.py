@@ -205,3 +205,54 @@ def test_inspiral_central_differences_full_grid_4096x256():
                   flush=True)
             assert abs(fd - dtraj[e, k]) <= 1e-6 * scale[k]
     s.close()
+
+
+def _torch_orbit(r_start, q, a, dt, n):
+    """(r0, phi) at t = k dt/2, k = 0..2n, of the quadrupole-decay orbit
+    r0^4 = r_start^4 - (256/5) q t (M = 1), phi by the trapezoid rule of
+    Omega = 1 / (r0^(3/2) + a): differentiable in r_start and q."""
+    import torch
+    t = torch.arange(2 * n + 1, dtype=torch.float64) * (0.5 * dt)
+    r = (r_start ** 4 - (256.0 / 5.0) * q * t) ** 0.25
+    om = 1.0 / (r ** 1.5 + a)
+    phi = torch.cat([torch.zeros(1, dtype=torch.float64), torch.cumsum(0.25 * dt * (om[1:] + om[:-1]), 0)])
+    return torch.stack([r, phi], dim=1)
+
+
+def test_autograd_chains_through_an_orbit_law(oracle_mod):
+    # L = sum |w - target|^2 of the waveform of an inspiral whose table comes
+    # from a torch orbit law; dL/dr_start and dL/dq by autograd (the library's
+    # reverse sweep, then the law's own backward) against central differences
+    import torch
+    from paper_0909_4039_amd.autograd import waveform_moving
+    c = CASES[1]
+    dt = _dt(oracle_mod, c)
+    n = c["n"]
+    s = _solver(c, dt)
+    phi, pi = inputs.random_state(c["nr"], c["nth"], seed=87)
+    phi0 = torch.as_tensor(phi, device="cuda:0")
+    pi0 = torch.as_tensor(pi, device="cuda:0")
+    with torch.no_grad():
+        target = waveform_moving(s, phi0, pi0, _torch_orbit(torch.tensor(10.1, dtype=torch.float64), 0.06,
+                                                              c["a"], dt, n), 0.9, n, c["robs"])
+
+    def loss(r_start, q, amp):
+        w = waveform_moving(s, phi0, pi0, _torch_orbit(r_start, q, c["a"], dt, n), amp, n, c["robs"])
+        return torch.sum(torch.abs(w - target) ** 2)
+
+    r_start = torch.tensor(10.0, dtype=torch.float64, requires_grad=True)
+    q = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    amp = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    L = loss(r_start, q, amp)
+    L.backward()
+    print(f"[gpu] orbit-law chain: L={L.item():.6e} dL/dr={r_start.grad.item():.10e} "
+          f"dL/dq={q.grad.item():.10e} dL/damp={amp.grad.item():.10e}", flush=True)
+    with torch.no_grad():
+        for name, grad, f, h in (("r_start", r_start.grad, lambda x: loss(x, q, amp), 1e-6),
+                                 ("q", q.grad, lambda x: loss(r_start, x, amp), 1e-6),
+                                 ("amp", amp.grad, lambda x: loss(r_start, q, x), 1e-6)):
+            x0 = {"r_start": r_start, "q": q, "amp": amp}[name].detach()
+            fd = (f(x0 + h) - f(x0 - h)).item() / (2 * h)
+            print(f"[gpu] {name}: autograd {grad.item():.10e} fd {fd:.10e}", flush=True)
+            assert grad.item() == pytest.approx(fd, rel=1e-5)
+    s.close()
