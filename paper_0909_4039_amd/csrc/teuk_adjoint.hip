@@ -128,8 +128,7 @@ __device__ __forceinline__ void apipe_init(APipe& st, int olo, int ohi, int nth)
 
 struct AConsts {
     const double* ang;
-    const double* xr_i;   // radial log-derivative of the source Gaussian, integer / half nodes
-    const double* xr_h;
+    double xr_i, xr_h;    // this lane's radial log-derivative of the source Gaussian, integer / half node
     const double (*srad)[N_RAD_USED][WAVE];
     int lane, nth, c, iobs;
     unsigned cu;
@@ -180,7 +179,7 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
             if constexpr (MOV)
                 grad_add(acc_i, K.dt, yQ, gth, S.rho1, S.x1, S.ph1, 1.0);
             else
-                grad_add(acc_i, K.dt, yQ, gth, qi.gr, K.xr_i[K.cu], S.ph1, S.t1);
+                grad_add(acc_i, K.dt, yQ, gth, qi.gr, K.xr_i, S.ph1, S.t1);
         }
     }
     // ---- B: reverse predictor at half row H
@@ -209,7 +208,7 @@ __device__ __forceinline__ void apipe_iter(APipe& st, const AConsts& K, const AS
             if constexpr (MOV)
                 grad_add(acc_h, K.hdt, ahq, gth, S.rho0, S.x0, S.ph0, 1.0);
             else
-                grad_add(acc_h, K.hdt, ahq, gth, qh.gr, K.xr_h[K.cu], S.ph0, S.t0);
+                grad_add(acc_h, K.hdt, ahq, gth, qh.gr, K.xr_h, S.ph0, S.t0);
         }
     }
     // ---- C: Phi adjoint of output row R
@@ -321,8 +320,8 @@ __device__ __forceinline__ void adj_step_body(const double* __restrict__ lp, con
     const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(double));
     AConsts K;
     K.ang = ang;
-    K.xr_i = rad_i + (int64_t)R_XR * A.stride;
-    K.xr_h = rad_h + (int64_t)R_XR * A.stride;
+    K.xr_i = MOV ? 0.0 : rad_i[(int64_t)R_XR * A.stride + cu];
+    K.xr_h = MOV ? 0.0 : rad_h[(int64_t)R_XR * A.stride + cu];
     K.srad = srad;
     K.lane = lane;
     K.nth = nth;
