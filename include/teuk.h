@@ -274,6 +274,21 @@ int teuk_batch_destroy(teuk_batch* b);
 int teuk_batch_bind(teuk_batch* b, int32_t i, void* phi, void* pi, void* phi_next, void* pi_next, void* wave,
                     int64_t wave_rows);
 
+/* Moving source for instance i (an inspiral, as for teuk_set_trajectory):
+ * r0_phase is a host array of n_half pairs (r0, phi) at t = k dt/2 counted
+ * from the batch's step 0, so batch step s uses entries 2s (predictor) and
+ * 2s + 1 (corrector); n_half >= 2 max_steps.  The instance keeps its
+ * descriptor's amplitude and widths and needs a source (r0 != 0 in its
+ * descriptor; TEUK_ESTATE otherwise).  Results equal, bit for bit, a
+ * single-mode run given the same table at step 0.  NULL returns the
+ * instance to its fixed orbit.  Synchronises the batch's stream.  Batches
+ * with a moving instance run a separate build of the batch kernels; when a
+ * call switches between the two, a captured graph is dropped
+ * (teuk_batch_step then launches directly; capture again for replays).
+ * TEUK_EINVAL for a short table or an entry with r0 <= r+ or a non-finite
+ * value. */
+int teuk_batch_set_trajectory(teuk_batch* b, int32_t i, const double* r0_phase, int64_t n_half);
+
 /* Advance every instance n steps (Eqs. 13-14 with source and boundary
  * conditions): replays of the captured graph while at least its step count
  * remains, then direct launches.  TEUK_EINVAL past max_steps. */

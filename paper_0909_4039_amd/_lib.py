@@ -63,6 +63,7 @@ _SIGS = {
     "teuk_batch_create": (ctypes.c_int, [_I32, ctypes.POINTER(TeukDesc), _I64, _P, ctypes.POINTER(_P)]),
     "teuk_batch_destroy": (ctypes.c_int, [_P]),
     "teuk_batch_bind": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _I64]),
+    "teuk_batch_set_trajectory": (ctypes.c_int, [_P, _I32, _P, _I64]),
     "teuk_batch_step": (ctypes.c_int, [_P, _I64]),
     "teuk_batch_capture_graph": (ctypes.c_int, [_P, _I64]),
     "teuk_batch_set_tiling": (ctypes.c_int, [_P, _I32, _I32, _I32]),

@@ -78,6 +78,20 @@ class Batch:
             self.phi(i).copy_(torch.as_tensor(phi).to(self.device, torch.complex128))
             self.pi(i).copy_(torch.as_tensor(pi).to(self.device, torch.complex128))
 
+    def set_trajectory(self, i, r0_phase):
+        """Moving source for instance i: r0_phase[k] = (r0, phi) at t = k dt/2
+        from the batch's step 0 (numpy (n, 2), n >= 2 max_steps); None: its
+        fixed orbit."""
+        if r0_phase is None:
+            _check(_lib.lib().teuk_batch_set_trajectory(self._b, int(i), None, 0), self._b)
+            return
+        import numpy as np
+        tab = np.ascontiguousarray(r0_phase, dtype=np.float64)
+        if tab.ndim != 2 or tab.shape[1] != 2:
+            raise ValueError("r0_phase must have shape (n, 2)")
+        _check(_lib.lib().teuk_batch_set_trajectory(self._b, int(i), tab.ctypes.data_as(ctypes.c_void_p),
+                                                    tab.shape[0]), self._b)
+
     def step(self, n):
         _check(_lib.lib().teuk_batch_step(self._b, int(n)), self._b)
 

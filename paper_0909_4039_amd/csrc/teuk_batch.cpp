@@ -21,6 +21,9 @@ struct teuk_batch {
     std::vector<Geometry> geo;
     std::vector<BatchInst> inst;        // host mirror of the device descriptors
     std::vector<bool> bound;
+    std::vector<double> omega;          // fixed-orbit Omega of each instance (0: no source)
+    std::vector<bool> has_src;
+    std::vector<double*> rs0_mem;       // device r*0 rows of each instance, allocated on first use
     std::vector<void*> allocs;          // device tables and phase rows
     BatchInst* d_inst = nullptr;
     BatchClock* d_clock = nullptr;
@@ -30,7 +33,8 @@ struct teuk_batch {
     int persistent = 1;                 // launch form (see lw_batch_kernel / lw_batch_grid_kernel)
     int n_tiles[KB_MAX] = {0, 0};
     int cus = 0;
-    int per_cu[KB_MAX] = {1, 1};
+    int per_cu[2 * KB_MAX] = {1, 1, 1, 1};   // [2 (kb - 1) + moving]
+    int n_moving = 0;                   // instances with a moving source
     bool dirty = true;                  // descriptors changed since the last upload
     hipGraphExec_t graph = nullptr;
     int graph_launches = 0;             // launches of kblock steps per replay
@@ -63,6 +67,36 @@ int dev_copy(teuk_batch* b, void** dst, const void* src, size_t bytes) {
     b->allocs.push_back(*dst);
     BHIP(b, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
     return TEUK_OK;
+}
+
+// Phase rows of every step the batch may take, with the single-mode step's
+// expressions: row k = e^{-i m w(t_k)}, e^{-i m w(t_k + dt/2)}, where w =
+// Omega t for a fixed orbit and the table's phi (entries 2k, 2k + 1,
+// clamped to the table) for a moving one; rs0 (moving only) gets r*(r0) of
+// the same entries.
+void fill_phases(const Geometry& g, double omega, double dt, int64_t rows, const double* traj, int64_t n_half,
+                 std::vector<double>& ph, std::vector<double>* rs0) {
+    ph.assign((size_t)rows * 4, 0.0);
+    if (rs0) rs0->assign((size_t)rows * 2, 0.0);
+    for (int64_t k = 0; k < rows; ++k) {
+        double w0, w1;
+        if (traj) {
+            const int64_t e = std::min<int64_t>(2 * k, n_half - 2);
+            const double* en = &traj[2 * e];
+            w0 = g.m * en[1];
+            w1 = g.m * en[3];
+            (*rs0)[2 * k + 0] = rstar_of_delta(en[0] - g.rp, g.a, g.M);
+            (*rs0)[2 * k + 1] = rstar_of_delta(en[2] - g.rp, g.a, g.M);
+        } else {
+            double t = 0.0 + double(k - 0) * dt;
+            w0 = g.m * omega * t;
+            w1 = g.m * omega * (t + 0.5 * dt);
+        }
+        ph[4 * k + 0] = std::cos(w0);
+        ph[4 * k + 1] = -std::sin(w0);
+        ph[4 * k + 2] = std::cos(w1);
+        ph[4 * k + 3] = -std::sin(w1);
+    }
 }
 
 // Tiles per instance and their prefix for every kb at the current rows.
@@ -109,7 +143,7 @@ int upload(teuk_batch* b) {
 int grid_blocks(const teuk_batch* b, int kb) {
     if (!b->persistent) return b->n_tiles[kb - 1];   // one workgroup per tile
     // as many workgroups as stay resident, a multiple of the 8 XCDs
-    int resident = std::max(8, (b->cus * b->per_cu[kb - 1]) / 8 * 8);
+    int resident = std::max(8, (b->cus * b->per_cu[2 * (kb - 1) + (b->n_moving > 0 ? 1 : 0)]) / 8 * 8);
     int need = (b->n_tiles[kb - 1] + 7) / 8 * 8;
     return std::max(8, std::min(resident, need));
 }
@@ -126,6 +160,7 @@ int launch(teuk_batch* b, int kb, bool record, int step_off, int launch_off) {
     a.persistent = b->persistent;
     a.step_off = step_off;
     a.launch_off = launch_off;
+    a.moving = b->n_moving > 0 ? 1 : 0;
     launch_batch_step(a, grid_blocks(b, kb), b->stream);
     BHIP(b, hipGetLastError());
     return TEUK_OK;
@@ -155,12 +190,16 @@ static int init_batch(teuk_batch* b, int32_t n, const teuk_desc* d, int64_t max_
     b->geo.resize(n);
     b->inst.resize(n);
     b->bound.assign(n, false);
+    b->omega.assign(n, 0.0);
+    b->has_src.assign(n, false);
+    b->rs0_mem.assign(n, nullptr);
     int rc = TEUK_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return TEUK_EDEVICE;
-    for (int kb = 1; kb <= KB_MAX; ++kb) b->per_cu[kb - 1] = batch_blocks_per_cu(kb);
+    for (int kb = 1; kb <= KB_MAX; ++kb)
+        for (int mv = 0; mv < 2; ++mv) b->per_cu[2 * (kb - 1) + mv] = batch_blocks_per_cu(kb, mv != 0);
     for (int i = 0; i < n && rc == TEUK_OK; ++i) {
         const teuk_desc& e = d[i];
         Geometry& g = b->geo[i];
@@ -191,17 +230,10 @@ static int init_batch(teuk_batch* b, int32_t n, const teuk_desc* d, int64_t max_
             omega = orbit_omega(e.r0, g.a, g.M);
             build_source(g, rstar_of_delta(e.r0 - g.rp, g.a, g.M), sr * g.dr, sth * g.dth, e.amp);
         }
-        // phase rows of every step the batch may take, with the single-mode
-        // step's expression for t and the phase
-        std::vector<double> ph((size_t)(max_steps + KB_MAX) * 4);
-        for (int64_t k = 0; k < max_steps + KB_MAX; ++k) {
-            double t = 0.0 + double(k - 0) * e.dt;
-            double w0 = g.m * omega * t, w1 = g.m * omega * (t + 0.5 * e.dt);
-            ph[4 * k + 0] = std::cos(w0);
-            ph[4 * k + 1] = -std::sin(w0);
-            ph[4 * k + 2] = std::cos(w1);
-            ph[4 * k + 3] = -std::sin(w1);
-        }
+        b->omega[i] = omega;
+        b->has_src[i] = e.r0 != 0.0;
+        std::vector<double> ph;
+        fill_phases(g, omega, e.dt, max_steps + KB_MAX, nullptr, 0, ph, nullptr);
         BatchInst& I = b->inst[i];
         std::memset(&I, 0, sizeof(I));
         void *ri = nullptr, *rh = nullptr, *an = nullptr, *pp = nullptr;
@@ -222,6 +254,11 @@ static int init_batch(teuk_batch* b, int32_t n, const teuk_desc* d, int64_t max_
         I.hdt = 0.5 * e.dt;
         I.inv_dr = 1.0 / g.dr;
         I.m2ma = -2.0 * g.m * g.a;
+        const double sr = (e.sigma_r_cells > 0.0 ? e.sigma_r_cells : 2.0) * g.dr;
+        I.rs0tab = nullptr;
+        I.two_sr2 = 2.0 * sr * sr;
+        I.rmin = g.rmin;
+        I.dr = g.dr;
     }
     if (rc == TEUK_OK) {
         set_rows(b, 0);
@@ -438,6 +475,59 @@ int teuk_batch_autotune(teuk_batch* b, int32_t launches_per_trial, int32_t* rows
     if (kb_out) *kb_out = best_kb;
     if (persistent_out) *persistent_out = best_form;
     return TEUK_OK;
+}
+
+static int teuk_batch_set_trajectory_impl(teuk_batch* b, int32_t i, const double* r0_phase, int64_t n_half) {
+    if (!b) return TEUK_EINVAL;
+    if (b->status != TEUK_OK) return b->status;
+    if (i < 0 || i >= b->n) return bfail(b, TEUK_EINVAL, "instance %d out of range", i);
+    const Geometry& g = b->geo[i];
+    BatchInst& I = b->inst[i];
+    const int64_t rows = b->max_steps + KB_MAX;
+    if (r0_phase) {
+        if (!b->has_src[i]) return bfail(b, TEUK_ESTATE, "instance %d has no source (r0 = 0 in its descriptor)", i);
+        if (n_half < 2 * b->max_steps || n_half > ((int64_t)1 << 34))
+            return bfail(b, TEUK_EINVAL, "the table needs 2 max_steps = %lld entries, it has %lld",
+                         (long long)(2 * b->max_steps), (long long)n_half);
+        for (int64_t k = 0; k < n_half; ++k)
+            if (!(r0_phase[2 * k] > g.rp) || !std::isfinite(r0_phase[2 * k]) || !std::isfinite(r0_phase[2 * k + 1]))
+                return bfail(b, TEUK_EINVAL, "orbit entry %lld: r0 must exceed r+ and both values be finite",
+                             (long long)k);
+    } else if (!I.rs0tab) {
+        return TEUK_OK;   // already a fixed orbit
+    }
+    std::vector<double> ph, rs0;
+    fill_phases(g, b->omega[i], I.dt, rows, r0_phase, n_half, ph, r0_phase ? &rs0 : nullptr);
+    // no launch may be reading the rows being replaced
+    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, hipMemcpy((void*)I.phase, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice));
+    const bool was_moving = I.rs0tab != nullptr;
+    if (r0_phase) {
+        if (!b->rs0_mem[i]) {
+            void* p = nullptr;
+            int rc = dev_copy(b, &p, rs0.data(), rs0.size() * sizeof(double));
+            if (rc != TEUK_OK) return rc;
+            b->rs0_mem[i] = (double*)p;
+        } else {
+            BHIP(b, hipMemcpy(b->rs0_mem[i], rs0.data(), rs0.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+        I.rs0tab = b->rs0_mem[i];
+    } else {
+        I.rs0tab = nullptr;   // its rows stay allocated for a later table
+    }
+    const int before = b->n_moving;
+    b->n_moving += (I.rs0tab != nullptr ? 1 : 0) - (was_moving ? 1 : 0);
+    if ((before > 0) != (b->n_moving > 0)) drop_graph(b);   // a captured graph holds the other kernel build
+    b->dirty = true;
+    return TEUK_OK;
+}
+
+int teuk_batch_set_trajectory(teuk_batch* b, int32_t i, const double* r0_phase, int64_t n_half) {
+    try {
+        return teuk_batch_set_trajectory_impl(b, i, r0_phase, n_half);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return bfail(b, TEUK_EDEVICE, "host allocation failed");
+    }
 }
 
 int teuk_batch_current(teuk_batch* b) { return b ? (int)(b->launches & 1) : TEUK_EINVAL; }

@@ -169,6 +169,10 @@ struct BatchInst {
     int32_t nr, nth, rows, iobs;
     int32_t first_tile[KB_MAX];
     double dt, hdt, inv_dr, m2ma, alpha;
+    // moving source: [rows][2] r*0 at t_k and t_k + dt/2 (NULL: fixed orbit),
+    // with the Gaussian's 2 sr^2 and the grid's r*_min, dr*
+    const double* rs0tab;
+    double two_sr2, rmin, dr;
 };
 
 // Device clock of a batch: steps taken and launches made (the launch
@@ -188,6 +192,7 @@ struct BatchArgs {
     int32_t persistent;       // 1: resident grid walking the tile list; 0: one workgroup per tile
     int32_t step_off;         // this launch's step and launch count relative to the clock
     int32_t launch_off;
+    int32_t moving;           // 1: some instance has a moving source (the kernels built for it)
 };
 
 constexpr int WAVE = 64;
@@ -202,7 +207,7 @@ void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs
 void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s);
 void launch_batch_advance(BatchClock* clock, int steps, int launches, hipStream_t s);
 void launch_batch_extract(const BatchInst* inst, int n_inst, int max_nth, const BatchClock* clock, hipStream_t s);
-int batch_blocks_per_cu(int kb);
+int batch_blocks_per_cu(int kb, bool moving);
 void launch_adjoint_step(const AdjArgs& a, hipStream_t s);
 void launch_adjoint_init(double* lp, double* lq, const double* g_row, int64_t n, int nr, int iobs, double alpha,
                          hipStream_t s);

@@ -399,6 +399,7 @@ typedef __attribute__((address_space(4))) const double* cdbl;
 // Per-tile constants of a batched launch, read from the instance's
 // descriptor, phase table and the clock (constant memory: reloaded where
 // that frees registers).
+template <bool MOV>
 struct InstParams {
     cinst I;
     cclock clk;
@@ -423,19 +424,19 @@ struct InstParams {
         const int64_t row = clk->step + step_off + q;
         return (record && I->wave != nullptr && row < I->wave_cap) ? row : -1;
     }
-    // batched instances have fixed orbits
-    __device__ bool moving() const { return false; }
-    __device__ double rs0(int) const { return 0.0; }
-    __device__ double two_sr2() const { return 1.0; }
-    __device__ double rmin() const { return 0.0; }
-    __device__ double dr() const { return 0.0; }
+    // moving source (compiled in only for batches that have one): i as for ph
+    __device__ bool moving() const { return MOV && I->rs0tab != nullptr; }
+    __device__ double rs0(int i) const { return I->rs0tab[2 * (clk->step + step_off + (i >> 1)) + (i & 1)]; }
+    __device__ double two_sr2() const { return I->two_sr2; }
+    __device__ double rmin() const { return I->rmin; }
+    __device__ double dr() const { return I->dr; }
 };
 
-template <int KB>
+template <int KB, bool MOV>
 __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, const BatchArgs& B,
                                            FwdLds<double, KB>* lds) {
     constexpr int SO = WAVE - 2 * KB;
-    const InstParams P{I, clk, B.record, B.step_off};
+    const InstParams<MOV> P{I, clk, B.record, B.step_off};
     const int src = (int)((clk->launches + B.launch_off) & 1);
     const int n_strips = (I->nr + SO - 1) / SO;
     const int ngrp = (n_strips + WG_WAVES - 1) / WG_WAVES;
@@ -449,8 +450,10 @@ __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, 
 
 // Persistent form: the grid holds as many workgroups as stay resident and
 // the 8 XCDs each walk a contiguous range of the tile list, so strips that
-// share halo columns and rows stay in one L2.
-template <int KB>
+// share halo columns and rows stay in one L2.  MOV: the batch has instances
+// with a moving source (a separate build, so fixed-orbit batches keep the
+// registers of the kernel without it).
+template <int KB, bool MOV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_kernel(BatchArgs B) {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     __shared__ FwdLds<double, KB> lds_all[WG_WAVES];
@@ -462,13 +465,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     int i = 0;
     for (int t = t_lo + kx; t < t_hi; t += nbx) {
         while (i + 1 < B.n_inst && insts[i + 1].first_tile[KB - 1] <= t) ++i;
-        batch_tile<KB>(insts + i, clk, t, wid, B, &lds_all[wid]);
+        batch_tile<KB, MOV>(insts + i, clk, t, wid, B, &lds_all[wid]);
     }
 }
 
 // Grid form: one workgroup per tile (XCD-aware order); the instance is
 // found by bisection over the tiles' prefix.
-template <int KB>
+template <int KB, bool MOV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lw_batch_grid_kernel(BatchArgs B) {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     __shared__ FwdLds<double, KB> lds_all[WG_WAVES];
@@ -481,23 +484,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         if (insts[mid].first_tile[KB - 1] <= t) lo = mid;
         else hi = mid - 1;
     }
-    batch_tile<KB>(insts + lo, clk, t, wid, B, &lds_all[wid]);
+    batch_tile<KB, MOV>(insts + lo, clk, t, wid, B, &lds_all[wid]);
 }
 
-int batch_blocks_per_cu(int kb) {
+// Resident workgroups per CU of the persistent kernel, per kb and form
+// (index 2 (kb - 1) + moving).
+int batch_blocks_per_cu(int kb, bool moving) {
     int n = 0;
-    hipError_t e = (kb == 2) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_batch_kernel<2>, WAVE * WG_WAVES, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_batch_kernel<1>, WAVE * WG_WAVES, 0);
+    auto k = kb == 2 ? (moving ? lw_batch_kernel<2, true> : lw_batch_kernel<2, false>)
+                     : (moving ? lw_batch_kernel<1, true> : lw_batch_kernel<1, false>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, WAVE * WG_WAVES, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 void launch_batch_step(const BatchArgs& a, int blocks, hipStream_t s) {
+    const bool mv = a.moving != 0;
     if (a.persistent) {
-        if (a.kb == 2) hipLaunchKernelGGL(lw_batch_kernel<2>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a);
-        else hipLaunchKernelGGL(lw_batch_kernel<1>, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a);
+        auto k = a.kb == 2 ? (mv ? lw_batch_kernel<2, true> : lw_batch_kernel<2, false>)
+                           : (mv ? lw_batch_kernel<1, true> : lw_batch_kernel<1, false>);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a);
     } else {
-        if (a.kb == 2) hipLaunchKernelGGL(lw_batch_grid_kernel<2>, dim3(a.n_tiles), dim3(WAVE * WG_WAVES), 0, s, a);
-        else hipLaunchKernelGGL(lw_batch_grid_kernel<1>, dim3(a.n_tiles), dim3(WAVE * WG_WAVES), 0, s, a);
+        auto k = a.kb == 2 ? (mv ? lw_batch_grid_kernel<2, true> : lw_batch_grid_kernel<2, false>)
+                           : (mv ? lw_batch_grid_kernel<1, true> : lw_batch_grid_kernel<1, false>);
+        hipLaunchKernelGGL(k, dim3(a.n_tiles), dim3(WAVE * WG_WAVES), 0, s, a);
     }
 }
 
