@@ -222,6 +222,66 @@ def time_batched(steps=200, graph_steps=20):
             "graph_steps": graph_steps}
 
 
+def time_inspiral_modes(steps=1000, graph_steps=20):
+    """The m = 1..8 modes of one inspiral (a = 0.9, s = -2, 8192 x 256 each,
+    source from r0 = 10 decaying with mass ratio 1e-4, zero initial data,
+    waveforms recorded): updates/s of 8 single-mode solvers stepped one
+    after another (each autotuned) against one batch of the 8 modes (moving
+    build, autotuned, replayed from a captured graph).  Results are bitwise
+    identical between the two."""
+    import torch
+    from paper_0909_4039_amd import inputs, workloads
+    from paper_0909_4039_amd.batch import Batch, make_desc
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    W = workloads.KERR_SOURCE   # the 8192 x 256 single-mode workload's grid and orbit
+    modes = list(range(1, 9))
+    total = steps + 2 * graph_steps
+    dts = [suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, m, W.s, W.steps) for m in modes]
+    dt = min(dts)   # one time step for all modes, so they share the orbit table
+    table = inputs.inspiral_trajectory(W.r0, W.a, W.M, 1e-4, dt, total)
+    pts = W.nr * W.nth * len(modes)
+    solvers = []
+    for m in modes:
+        s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, m, W.s, dt)
+        s.set_source(W.r0, W.amp)
+        s.set_trajectory(table)
+        s.set_observer(W.rstar_obs, total + 1)
+        s.autotune(5)
+        solvers.append(s)
+    for s in solvers:
+        s.step(graph_steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    per_mode = time.perf_counter() - t
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+    descs = [make_desc(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, m, dt, s=W.s, r0=W.r0, amp=W.amp,
+                       rstar_obs=W.rstar_obs) for m in modes]
+    b = Batch(descs, total)
+    for i in range(len(modes)):
+        b.set_trajectory(i, table)
+    rows, kb, persistent = b.autotune(5)
+    b.capture_graph(graph_steps)
+    b.step(graph_steps)
+    b.synchronize()
+    t = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    batched = time.perf_counter() - t
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": "inspiral_modes_m1-8_a0.9_8192x256", "instances": len(modes), "points": pts,
+            "steps": steps, "mass_ratio": 1e-4, "per_mode_updates_per_s": pts * steps / per_mode,
+            "batched_updates_per_s": pts * steps / batched, "batched_over_per_mode": per_mode / batched,
+            "batch_rows_per_wave": rows, "batch_steps_per_launch": kb, "batch_persistent": persistent}
+
+
 def time_small_and_mid():
     """Two more single-mode workloads, each autotuned.
 
@@ -486,6 +546,7 @@ def main():
         out["adjoint"] = time_adjoint()
     if not args.no_batched:
         out["batched"] = time_batched()
+        out["inspiral_modes"] = time_inspiral_modes()
     if not args.no_others:
         out["other_workloads"] = time_small_and_mid()
     if not args.no_copy:
