@@ -47,6 +47,16 @@ namespace teuk {
 // The differences arrive unscaled (u_{i+1} - u_i): 1/dr* is folded into b
 // (one multiply) and into CR (the radial fields CRR and WBN are scaled when
 // the tile loads them, and m2ma_idr = -2 m a / dr*).
+//
+// The means enter as sums, with no multiply by 1/2: the predictor works
+// with twice its values (s = u_i + u_{i+1}, so f = s/2) and produces twice
+// the half-step values; the corrector then sees four times its means and
+// twice its differences.  The stage is linear, so scaling its inputs by 2
+// (predictor) or 4 (corrector) is undone by powers of two folded into
+// constants: b and CR carry 2/dr* (idr = 2/dr*), the source slots hold 2T
+// (predictor) and 4T (corrector), and the corrector's tau is dt/4.  Powers
+// of two scale exactly in binary floating point, so every rounded result
+// equals that of the form with explicit means.
 template <typename R>
 struct Stage {
     cx<R> phi, pi_part;
@@ -116,7 +126,7 @@ struct Consts {
     const R (*srad)[N_RAD_FWD][WAVE];
     const R (*ssrc)[2][WAVE];   // source radial factor [fused step][half/integer][lane]
     int lane, nth;
-    R keep, idr, dt, hdt, m2ma_idr;
+    R keep, idr, qdt, hdt, m2ma_idr;   // idr = 2/dr*, qdt = dt/4 (see stage())
 };
 
 // One iteration of a stage at its row index L with input row L = (p, q).
@@ -127,7 +137,6 @@ template <typename R>
 __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int ks, int L, cx<R> p, cx<R> q,
                                           cx<R> ph0, cx<R> ph1, R* wave, int64_t wrow, int wl, int rlo,
                                           int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
-    const R half = R(0.5);
     const cx<R> zero = {R(0), R(0)};
     const int P = L - 1, Q = L - 2;
     const cx<R> up = st.up, uq = st.uq;
@@ -138,8 +147,8 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
     cx<R> pbL = zero, Qb, dP, dQ;   // Qb, dP, dQ are read only by A2, which implies A1 ran
     if (L < st.ihi) {
         cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
-        pbL = half * (p + p1);
-        Qb = half * (q + q1);
+        pbL = p + p1;            // twice the mean (see stage())
+        Qb = q + q1;
         dP = p1 - p;             // unscaled: 1/dr* is folded into the stage
         dQ = q1 - q;
         if (wrow >= 0 && L >= rlo && L < rhi) {
@@ -154,8 +163,8 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
         cx<R> Lf = rfma(wp, pbL, st.pb_acc);
         cx<R> hQ = rfma(st.hD, Lf, st.hQp);
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
-        phL = half * (st.hP + hPm);
-        Qh = half * (hQ + hQm);
+        phL = st.hP + hPm;       // twice twice the mean: the half-step values are doubled
+        Qh = hQ + hQm;
         dhP = st.hP - hPm;
         dhQ = hQ - hQm;
     }
@@ -186,7 +195,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
         const Ang<R> g = load_ang(K.ang, P);
         const Rad<R> qi = lds_rad_fwd<R>(K.srad[1], K.lane);   // integer point c
         const R gr = lds_lane(K.ssrc[ks][1], K.lane);
-        Stage<R> o = stage(qi, gr, g, K.m2ma_idr, K.idr, K.dt, ph1, up, uq, phL, Qh, dhP, dhQ);
+        Stage<R> o = stage(qi, gr, g, K.m2ma_idr, K.idr, K.qdt, ph1, up, uq, phL, Qh, dhP, dhQ);
         st.nQp = o.pi_part;
         st.nD = o.dw;
         outP = K.keep * o.phi;
@@ -221,7 +230,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
     // radial numerators of this wavefront's columns (CRR and WBN, which
     // multiply r* differences only, carry the 1/dr* of those differences)
-    const R idr = A.inv_dr();
+    const R idr = R(2) * A.inv_dr();   // 2/dr*: the stage sees doubled differences (see stage())
     R (*srad)[N_RAD_FWD][WAVE] = lds->rad;
     for (int k = 0; k < 2 * N_RAD_FWD; ++k) {
         const int loc = k / N_RAD_FWD, f = k % N_RAD_FWD;
@@ -241,7 +250,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
             } else {
                 v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * A.stride() + cu];
             }
-            lds->src[k][loc][lane] = v;
+            lds->src[k][loc][lane] = v * (loc == 0 ? R(2) : R(4));   // 2T predictor, 4T corrector
         }
     const int j0 = chunk * A.rows();
     const int jend = min(j0 + A.rows(), nth);
@@ -256,7 +265,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     K.nth = nth;
     K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
     K.idr = idr;
-    K.dt = A.dt();
+    K.qdt = R(0.25) * A.dt();
     K.hdt = A.hdt();
     K.m2ma_idr = A.m2ma() * idr;
     // recorder: the strip holding columns iobs and iobs+1 among its lanes
