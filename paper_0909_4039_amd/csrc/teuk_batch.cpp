@@ -498,23 +498,28 @@ static int teuk_batch_set_trajectory_impl(teuk_batch* b, int32_t i, const double
     }
     std::vector<double> ph, rs0;
     fill_phases(g, b->omega[i], I.dt, rows, r0_phase, n_half, ph, r0_phase ? &rs0 : nullptr);
-    // no launch may be reading the rows being replaced
-    BHIP(b, hipStreamSynchronize(b->stream));
-    BHIP(b, hipMemcpy((void*)I.phase, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice));
     const bool was_moving = I.rs0tab != nullptr;
-    if (r0_phase) {
-        if (!b->rs0_mem[i]) {
-            void* p = nullptr;
-            int rc = dev_copy(b, &p, rs0.data(), rs0.size() * sizeof(double));
-            if (rc != TEUK_OK) return rc;
-            b->rs0_mem[i] = (double*)p;
-        } else {
-            BHIP(b, hipMemcpy(b->rs0_mem[i], rs0.data(), rs0.size() * sizeof(double), hipMemcpyHostToDevice));
-        }
-        I.rs0tab = b->rs0_mem[i];
-    } else {
-        I.rs0tab = nullptr;   // its rows stay allocated for a later table
+    // no launch may be reading the rows being replaced, and the copies are
+    // ordered on the batch's stream (which need not synchronise with the
+    // null stream); the stream is synchronised again before the host
+    // vectors go away, on the error paths too
+    BHIP(b, hipStreamSynchronize(b->stream));
+    if (r0_phase && !b->rs0_mem[i]) {
+        b->allocs.reserve(b->allocs.size() + 1);   // a failed push_back must not lose the block
+        void* p = nullptr;
+        BHIP(b, hipMalloc(&p, rs0.size() * sizeof(double)));
+        b->allocs.push_back(p);
+        b->rs0_mem[i] = (double*)p;
     }
+    hipError_t e = hipMemcpyAsync((void*)I.phase, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess && r0_phase)
+        e = hipMemcpyAsync(b->rs0_mem[i], rs0.data(), rs0.size() * sizeof(double), hipMemcpyHostToDevice,
+                           b->stream);
+    const hipError_t es = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return bfail(b, TEUK_EDEVICE, "orbit table upload: %s", hipGetErrorString(e));
+    I.rs0tab = r0_phase ? b->rs0_mem[i] : nullptr;   // cleared rows stay allocated for a later table
     const int before = b->n_moving;
     b->n_moving += (I.rs0tab != nullptr ? 1 : 0) - (was_moving ? 1 : 0);
     if ((before > 0) != (b->n_moving > 0)) drop_graph(b);   // a captured graph holds the other kernel build
