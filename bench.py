@@ -525,7 +525,10 @@ def main():
                    "initial_data": "zero, source on", "steps_per_launch": kb,
                    "rows_per_wave": tiling[0]},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": measured_traffic(64),
+                     "frac": achieved / HBM_PEAK,
+                     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE), or None
+                     "traffic": (lambda t: t["bytes_per_launch"] if t else None)(measured_traffic(64)),
+                     "traffic_detail": measured_traffic(64),
                      "kernel": f"lw_step_kernel<double, {kb}>",
                      "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
         # update rate expressed as the bandwidth an unblocked step would need
