@@ -197,6 +197,45 @@ int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t 
 int teuk_adjoint_moving(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t n_steps, void* workspace,
                         int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dtraj, double* dL_damp);
 
+/* Gradient of a real loss of the waveform with respect to one parameter
+ * of the problem, with checkpointing (FP64, fixed orbit).  The parameter
+ * is the Kerr spin a (TEUK_PARAM_A), the mass M (TEUK_PARAM_M), the orbit
+ * radius r0 (TEUK_PARAM_R0) or the source amplitude (TEUK_PARAM_AMP).  a
+ * and M enter the operator K of Eqs. (13)-(14) through every coefficient,
+ * so unlike teuk_adjoint this needs the forward states:
+ *   dL/dp = sum_k Re <lambda^{k+1}, d step(u^k) / dp>,
+ * where lambda^{k+1} is the adjoint of u^{k+1} and the derivative of one
+ * step at fixed u^k is the central difference
+ *   [step_{p+h}(u^k) - step_{p-h}(u^k)] / (2h)
+ * of steps under the perturbed parameter (tables, source and Omega built
+ * for p +- h; error O(h^2), plus rounding of order eps/h).  The forward run
+ * from (phi0, pi0) at t_start keeps every C-th state (checkpoint_interval
+ * C; 0 picks ceil(sqrt(n_steps))); the reverse sweep recomputes each
+ * segment of C states from its checkpoint.  So memory is ceil(n/C) + C + 3
+ * states, and the cost is about five forward runs.  Contractions and their
+ * sum follow fixed orders (results repeat bit for bit).
+ *   dL_dwave: device, (n_steps + 1) x n_theta complex128, as teuk_adjoint.
+ *   phi0, pi0: device, n_theta x n_rstar complex128, the initial data (read).
+ *   workspace: device, teuk_param_gradient_workspace_bytes(ctx, n_steps, C)
+ *     bytes, 256-byte aligned.
+ *   dL_dparam: host (written).
+ *   dL_dphi0, dL_dpi0: device, may both be NULL; else they receive
+ *     lambda^0, as from teuk_adjoint.
+ * The context's bound state, time and observer are not touched.
+ * TEUK_EINVAL for an unknown parameter, h <= 0, a perturbed value outside
+ * the valid range (|a| >= M, r0 <= r+), or bad buffers; TEUK_ESTATE for
+ * TEUK_PARAM_R0 or TEUK_PARAM_AMP without a source; TEUK_ENOTSUP for FP32
+ * contexts or with an orbit table set. */
+#define TEUK_PARAM_A 0
+#define TEUK_PARAM_M 1
+#define TEUK_PARAM_R0 2
+#define TEUK_PARAM_AMP 3
+int64_t teuk_param_gradient_workspace_bytes(teuk_ctx* ctx, int64_t n_steps, int64_t checkpoint_interval);
+int teuk_param_gradient(teuk_ctx* ctx, int32_t param, double h, double rstar_obs, const void* dL_dwave,
+                        int64_t n_steps, double t_start, const void* phi0, const void* pi0,
+                        int64_t checkpoint_interval, void* workspace, int64_t workspace_bytes, double* dL_dparam,
+                        void* dL_dphi0, void* dL_dpi0);
+
 /* Autotuner (synchronous): times launches_per_trial launches (after one
  * warm-up launch) of every candidate tile shape -- theta rows per wavefront
  * in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256} clipped to

@@ -248,6 +248,23 @@ class Oracle:
         return d1, d2, dtraj, am.value
 
 
+def param_gradient_fd(nr, nth, rstar_min, rstar_max, a, M, m, s, dt, r0, amp, rstar_obs, param, h, G, n, phi0,
+                      pi0, t_start=0.0) -> float:
+    """dL/dp for L = Re sum conj(G) w (w^0..w^n at rstar_obs) by the central
+    difference of two complete oracle runs, p + h and p - h, for p one of
+    "a", "M", "r0", "amp": the definition of the derivative, to O(h^2)."""
+    base = dict(a=a, M=M, r0=r0, amp=amp)
+    Ls = []
+    for sign in (1.0, -1.0):
+        q = dict(base)
+        q[param] += sign * h
+        o = Oracle(nr, nth, rstar_min, rstar_max, q["a"], q["M"], m, s, dt, r0=q["r0"], amp=q["amp"],
+                   rstar_obs=rstar_obs)
+        _, _, w = o.run(phi0, pi0, n, t_start)
+        Ls.append(float(np.sum((np.conj(G) * w).real)))
+    return (Ls[0] - Ls[1]) / (2.0 * h)
+
+
 def stable_dt(nr, nth, rstar_min, rstar_max, a, M, m, s, n_steps) -> float:
     """Time step rule for the explicit scheme.
 

@@ -10,6 +10,7 @@ LIB_PATH = os.environ.get("TEUK_LIB") or os.path.join(HERE, "libteuk.so")
 
 OK, EINVAL, ESTATE, EDEVICE, EUNSTABLE, ENOTSUP = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 64, 32
+PARAM_A, PARAM_M, PARAM_R0, PARAM_AMP = 0, 1, 2, 3   # parameters of teuk_param_gradient
 
 
 class TeukGrid(ctypes.Structure):
@@ -56,6 +57,9 @@ _SIGS = {
                                     ctypes.POINTER(_D)]),
     "teuk_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_set_adjoint_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "teuk_param_gradient_workspace_bytes": (_I64, [_P, _I64, _I64]),
+    "teuk_param_gradient": (ctypes.c_int, [_P, _I32, ctypes.c_double, ctypes.c_double, _P, _I64, ctypes.c_double,
+                                           _P, _P, _I64, _P, _I64, ctypes.POINTER(ctypes.c_double), _P, _P]),
     "teuk_adjoint_moving": (ctypes.c_int, [_P, ctypes.c_double, _P, _I64, _P, _I64, _P, _P, _P,
                                            ctypes.POINTER(ctypes.c_double)]),
     "teuk_get_adjoint_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),

@@ -939,6 +939,241 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
     }
 }
 
+// ------------------------------------------------------- parameter gradients
+
+// One FP64 step of x (its tables, source and tiling; one step per launch)
+// from (ip, iq) into (op, oq) at time t, with a fixed-orbit source; records
+// no waveform and leaves x's bound state, step count and time alone.
+static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t) {
+    const Geometry& g = x->geo;
+    StepArgs<double> a = step_args<double>(x);
+    a.kb = 1;
+    const int so = WAVE - 2;
+    a.n_strips = (int)((g.nr + so - 1) / so);
+    a.n_tiles = a.n_strips * a.n_chunks;
+    for (int q = 0; q < KB_MAX; ++q) {
+        const double tq = t + double(q) * x->dt;
+        const double w0 = g.m * x->Omega * tq, w1 = g.m * x->Omega * (tq + 0.5 * x->dt);
+        a.ph[2 * q][0] = std::cos(w0);
+        a.ph[2 * q][1] = -std::sin(w0);
+        a.ph[2 * q + 1][0] = std::cos(w1);
+        a.ph[2 * q + 1][1] = -std::sin(w1);
+        a.wave_row[q] = -1;
+    }
+    a.phi = ip;
+    a.pi = iq;
+    a.phi_out = op;
+    a.pi_out = oq;
+    launch_step_fp64(a, x->stream);
+    HIP_TRY(x, hipGetLastError());
+    return TEUK_OK;
+}
+
+// Workspace of a parameter gradient: two adjoint pairs, the reverse step's
+// gradient slots, ceil(n / C) checkpoints, C - 1 segment states, two
+// perturbed-step outputs, the dot product's block parts and one double per
+// step.  A state is Phi and Pi, complex128 [nth][nr] each.
+struct ParamLayout {
+    int64_t state, lam, slots, ckpt, seg, pert, parts, res, total, n_ckpt;
+};
+static ParamLayout param_layout(const teuk_ctx* c, int64_t n, int64_t C) {
+    ParamLayout L;
+    const int64_t npts = c->geo.nr * c->geo.nth;
+    L.state = round256(2 * npts * 16);
+    L.n_ckpt = n > 0 ? (n + C - 1) / C : 1;
+    L.lam = 0;
+    L.slots = L.lam + 2 * L.state;
+    L.ckpt = L.slots + round256(adjoint_slots_max(c->geo) * 3 * 8);
+    L.seg = L.ckpt + L.n_ckpt * L.state;
+    L.pert = L.seg + std::max<int64_t>(C - 1, 0) * L.state;
+    L.parts = L.pert + 2 * L.state;
+    L.res = L.parts + round256((int64_t)param_dot_parts() * 8);
+    L.total = L.res + round256(std::max<int64_t>(n, 1) * 8);
+    return L;
+}
+
+static int64_t default_interval(int64_t n) {
+    int64_t C = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1)));
+    return std::max<int64_t>(C, 1);
+}
+
+// The checkpointed sweep: forward from u^0 keeping every C-th state, then
+// segment by segment from the last, recompute the segment's states from its
+// checkpoint, and for each step k (descending) contract lambda^{k+1} with
+// step_{p+h}(u^k) - step_{p-h}(u^k) and take the reverse step to lambda^k.
+static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double alpha, const double* g, int64_t n,
+                       double t_start, const double* phi0, const double* pi0, int64_t C, char* ws,
+                       std::vector<double>& res, const double** lam0) {
+    const Geometry& geo = c->geo;
+    const ParamLayout L = param_layout(c, n, C);
+    const int64_t npts = geo.nr * geo.nth;
+    auto state = [&](int64_t off) { return (double*)(ws + off); };
+    auto pi_of = [&](double* phi) { return phi + 2 * npts; };
+    double* lam[2] = {state(L.lam), state(L.lam + L.state)};
+    double* slots = state(L.slots);
+    auto ckpt = [&](int64_t j) { return state(L.ckpt + j * L.state); };
+    auto seg = [&](int64_t j, int64_t i) { return i == 0 ? ckpt(j) : state(L.seg + (i - 1) * L.state); };
+    double* X = state(L.pert);
+    double* Y = state(L.pert + L.state);
+    double* parts = state(L.parts);
+    double* dres = state(L.res);
+    const double dt = c->dt;
+    // forward pass, keeping u^{jC}
+    HIP_TRY(c, hipMemcpyAsync(ckpt(0), phi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pi_of(ckpt(0)), pi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
+    double* cur = ckpt(0);
+    for (int64_t k = 0; k + 1 < n; ++k) {   // u^n itself is not needed
+        double* next = ((k + 1) % C == 0) ? ckpt((k + 1) / C) : (cur == X ? Y : X);
+        int rc = step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt);
+        if (rc != TEUK_OK) return rc;
+        cur = next;
+    }
+    // lambda^n = E^H g^n
+    launch_adjoint_init(lam[0], pi_of(lam[0]), g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    launch_fill_zero(slots, adjoint_slots_max(geo) * 3, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    AdjArgs a = adjoint_args(c, g, iobs, alpha, slots);
+    int li = 0;   // lam[li] holds lambda^{k+1}
+    for (int64_t j = L.n_ckpt - 1; j >= 0 && n > 0; --j) {
+        const int64_t k0 = j * C, k1 = std::min(k0 + C, n);
+        for (int64_t i = 1; i < k1 - k0; ++i) {
+            double* in = seg(j, i - 1);
+            double* out = seg(j, i);
+            int rc = step_at(c, in, pi_of(in), out, pi_of(out), t_start + double(k0 + i - 1) * dt);
+            if (rc != TEUK_OK) return rc;
+        }
+        for (int64_t k = k1 - 1; k >= k0; --k) {
+            double* u = seg(j, k - k0);
+            const double t = t_start + double(k) * dt;
+            int rc = step_at(xp, u, pi_of(u), X, pi_of(X), t);
+            if (rc == TEUK_OK) rc = step_at(xm, u, pi_of(u), Y, pi_of(Y), t);
+            if (rc != TEUK_OK) return rc;
+            launch_param_dot(lam[li], pi_of(lam[li]), X, pi_of(X), Y, pi_of(Y), 2 * npts, parts, dres + k,
+                             c->stream);
+            HIP_TRY(c, hipGetLastError());
+            adjoint_launch_args(c, a, 1, k + 1, t_start, true);
+            a.lp = lam[li];
+            a.lq = pi_of(lam[li]);
+            a.lp_out = lam[1 - li];
+            a.lq_out = pi_of(lam[1 - li]);
+            launch_adjoint_step(a, c->stream);
+            HIP_TRY(c, hipGetLastError());
+            li = 1 - li;
+        }
+    }
+    res.assign((size_t)std::max<int64_t>(n, 0), 0.0);
+    if (n > 0)
+        HIP_TRY(c, hipMemcpyAsync(res.data(), dres, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *lam0 = lam[li];   // lambda^0
+    return TEUK_OK;
+}
+
+int64_t teuk_param_gradient_workspace_bytes(teuk_ctx* c, int64_t n_steps, int64_t checkpoint_interval) {
+    if (!c || n_steps < 0 || checkpoint_interval < 0) return TEUK_EINVAL;
+    const int64_t C = checkpoint_interval > 0 ? checkpoint_interval : default_interval(n_steps);
+    return param_layout(c, n_steps, C).total;
+}
+
+static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double rstar_obs, const void* dL_dwave,
+                                    int64_t n_steps, double t_start, const void* phi0, const void* pi0,
+                                    int64_t checkpoint_interval, void* workspace, int64_t workspace_bytes,
+                                    double* dL_dparam, void* dL_dphi0, void* dL_dpi0) {
+    if (!c) return TEUK_EINVAL;
+    if (c->traj_n > 0) return fail(c, TEUK_ENOTSUP, "parameter gradients need a fixed orbit (no trajectory)");
+    if (param < TEUK_PARAM_A || param > TEUK_PARAM_AMP) return fail(c, TEUK_EINVAL, "unknown parameter %d", param);
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(c, TEUK_EINVAL, "h must be positive and finite");
+    if (!std::isfinite(t_start)) return fail(c, TEUK_EINVAL, "non-finite t_start");
+    if (checkpoint_interval < 0) return fail(c, TEUK_EINVAL, "negative checkpoint interval");
+    if (!dL_dparam) return fail(c, TEUK_EINVAL, "NULL dL_dparam");
+    if (!phi0 || !pi0 || (uintptr_t)phi0 % 16 != 0 || (uintptr_t)pi0 % 16 != 0)
+        return fail(c, TEUK_EINVAL, "phi0 and pi0 must be 16-byte aligned device buffers");
+    if ((param == TEUK_PARAM_R0 || param == TEUK_PARAM_AMP) && !c->has_src)
+        return fail(c, TEUK_ESTATE, "no source: teuk_set_source first");
+    const int64_t C = checkpoint_interval > 0 ? checkpoint_interval : default_interval(n_steps);
+    const ParamLayout L = param_layout(c, n_steps, C);
+    if (!dL_dwave || !workspace) return fail(c, TEUK_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % 256 != 0) return fail(c, TEUK_EINVAL, "workspace not 256-byte aligned");
+    if ((uintptr_t)dL_dwave % 16 != 0) return fail(c, TEUK_EINVAL, "dL_dwave must be 16-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(c, TEUK_EINVAL, "workspace of %lld B is smaller than the %lld B needed", (long long)workspace_bytes,
+                    (long long)L.total);
+    if ((dL_dphi0 == nullptr) != (dL_dpi0 == nullptr)) return fail(c, TEUK_EINVAL, "give both dL_dphi0 and dL_dpi0 or neither");
+    if (c->status != TEUK_OK) return c->status;
+    if (c->prec != TEUK_FP64) return fail(c, TEUK_ENOTSUP, "parameter gradients are FP64 only");
+    if (n_steps < 0) return fail(c, TEUK_EINVAL, "negative step count");
+    const Geometry& geo = c->geo;
+    int iobs;
+    double alpha;
+    if (!observer_index(geo, rstar_obs, iobs, alpha))
+        return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
+    // the two perturbed contexts: same grid, mode, dt, tiling and source, one parameter moved by +-h
+    teuk_grid gr{geo.nr, geo.nth, geo.rmin, geo.rmax};
+    double pa[2] = {geo.a, geo.a}, pM[2] = {geo.M, geo.M}, pr0[2] = {c->r0, c->r0}, pamp[2] = {c->amp, c->amp};
+    double* moved = param == TEUK_PARAM_A ? pa : param == TEUK_PARAM_M ? pM : param == TEUK_PARAM_R0 ? pr0 : pamp;
+    moved[0] += h;
+    moved[1] -= h;
+    struct Owned {   // the perturbed contexts are destroyed on every path
+        teuk_ctx* p = nullptr;
+        ~Owned() {
+            if (p) teuk_destroy(p);
+        }
+    } own[2];
+    teuk_ctx* x[2] = {nullptr, nullptr};
+    int rc = TEUK_OK;
+    for (int i = 0; i < 2 && rc == TEUK_OK; ++i) {
+        if (validate_phys(&gr, pa[i], pM[i], geo.s) != TEUK_OK) {
+            rc = fail(c, TEUK_EINVAL, "the parameter moved by %s h leaves the valid range", i == 0 ? "+" : "-");
+            break;
+        }
+        x[i] = own[i].p = new (std::nothrow) teuk_ctx();
+        if (!x[i]) {
+            rc = fail(c, TEUK_EDEVICE, "host allocation failed");
+            break;
+        }
+        rc = init_ctx(x[i], &gr, pa[i], pM[i], geo.m, geo.s, c->dt, TEUK_FP64, (void*)c->stream);
+        if (rc != TEUK_OK) {
+            rc = fail(c, TEUK_EDEVICE, "perturbed context: %s", x[i]->err);
+            break;
+        }
+        x[i]->rows = c->rows;
+        if (c->has_src) {
+            rc = teuk_set_source_impl(x[i], pr0[i], pamp[i], c->sig_r, c->sig_th);
+            if (rc != TEUK_OK) rc = fail(c, rc, "perturbed source: %s", x[i]->err);
+        }
+    }
+    std::vector<double> res;
+    const double* lam0 = nullptr;
+    if (rc == TEUK_OK)
+        rc = param_sweep(c, x[0], x[1], iobs, alpha, (const double*)dL_dwave, n_steps, t_start, (const double*)phi0,
+                         (const double*)pi0, C, (char*)workspace, res, &lam0);
+    if (rc != TEUK_OK) return rc;
+    // sum in step order, then the central difference's 1/(2h)
+    double sum = 0.0;
+    for (double v : res) sum += v;
+    *dL_dparam = sum / (2.0 * h);
+    if (dL_dphi0) {
+        const int64_t npts = geo.nr * geo.nth;
+        HIP_TRY(c, hipMemcpyAsync(dL_dphi0, lam0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(dL_dpi0, lam0 + 2 * npts, npts * 16, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return TEUK_OK;
+}
+
+int teuk_param_gradient(teuk_ctx* c, int32_t param, double h, double rstar_obs, const void* dL_dwave, int64_t n_steps,
+                        double t_start, const void* phi0, const void* pi0, int64_t checkpoint_interval,
+                        void* workspace, int64_t workspace_bytes, double* dL_dparam, void* dL_dphi0, void* dL_dpi0) {
+    try {
+        return teuk_param_gradient_impl(c, param, h, rstar_obs, dL_dwave, n_steps, t_start, phi0, pi0,
+                                        checkpoint_interval, workspace, workspace_bytes, dL_dparam, dL_dphi0,
+                                        dL_dpi0);
+    } catch (...) {  // no C++ exception crosses the ABI
+        return fail(c, TEUK_EDEVICE, "host allocation failed");
+    }
+}
+
 int teuk_check_finite(teuk_ctx* c) {
     if (!c) return TEUK_EINVAL;
     if (c->status != TEUK_OK) return c->status;

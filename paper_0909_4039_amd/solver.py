@@ -232,6 +232,47 @@ class Solver:
                   self._ctx)
         return dphi, dpi, dtraj[:2 * n], damp.value
 
+    def param_gradient(self, param, dL_dwave, n_steps, rstar_obs, phi0, pi0, h=None, t_start=0.0,
+                       checkpoint_interval=0, want_initial=False):
+        """Gradient of a real waveform loss with respect to one parameter of the
+        problem ("a", "M", "r0" or "amp"), by the library's checkpointed
+        reverse sweep from the initial data (phi0, pi0) at t_start (FP64, fixed
+        orbit).  dL_dwave is (n_steps + 1, n_theta) complex, as for ``adjoint``.
+        h is the central-difference step of one time step's parameter
+        derivative (default 1e-6 max(1, |p|)).  Returns dL/dp, or
+        (dL/dp, dL/dPhi0, dL/dPi0) with want_initial."""
+        names = {"a": _lib.PARAM_A, "M": _lib.PARAM_M, "r0": _lib.PARAM_R0, "amp": _lib.PARAM_AMP}
+        if param not in names:
+            raise ValueError(f"param must be one of {sorted(names)}")
+        value = {"a": self.params["a"], "M": self.params["M"],
+                 "r0": self.source[0] if self.source else 0.0, "amp": self.source[1] if self.source else 0.0}[param]
+        if h is None:
+            h = 1e-6 * max(1.0, abs(value))
+        n = int(n_steps)
+        g = torch.as_tensor(dL_dwave).to(self.device, torch.complex128).contiguous()
+        if g.shape != (n + 1, self.shape[0]):
+            raise ValueError(f"dL_dwave has shape {tuple(g.shape)}, expected {(n + 1, self.shape[0])}")
+        p0 = torch.as_tensor(phi0).to(self.device, torch.complex128).contiguous()
+        q0 = torch.as_tensor(pi0).to(self.device, torch.complex128).contiguous()
+        if p0.shape != self.shape or q0.shape != self.shape:
+            raise ValueError(f"initial data must have shape {self.shape}")
+        nbytes = check_int(_lib.lib().teuk_param_gradient_workspace_bytes(self._ctx, n, int(checkpoint_interval)))
+        ws = torch.empty((nbytes + 255) // 8 + 32, dtype=torch.float64, device=self.device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        dphi = torch.empty(self.shape, dtype=torch.complex128, device=self.device) if want_initial else None
+        dpi = torch.empty(self.shape, dtype=torch.complex128, device=self.device) if want_initial else None
+        out = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            check(_lib.lib().teuk_param_gradient(self._ctx, names[param], float(h), float(rstar_obs), g.data_ptr(), n,
+                                                 float(t_start), p0.data_ptr(), q0.data_ptr(),
+                                                 int(checkpoint_interval), ctypes.c_void_p(base + off),
+                                                 int(ws.numel() * 8 - off), ctypes.byref(out),
+                                                 dphi.data_ptr() if want_initial else None,
+                                                 dpi.data_ptr() if want_initial else None), self._ctx)
+        return (out.value, dphi, dpi) if want_initial else out.value
+
     def check_finite(self):
         """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""
         check(_lib.lib().teuk_check_finite(self._ctx), self._ctx)
