@@ -99,6 +99,7 @@ def time_adjoint(steps=None):
     import torch
     from paper_0909_4039_amd import inputs, workloads
     from paper_0909_4039_amd.solver import Solver, suggest_dt
+    import numpy as np
     W = workloads.ADJOINT
     n = steps or W.steps
     dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
@@ -135,6 +136,22 @@ def time_adjoint(steps=None):
         t = time.perf_counter()
         s.adjoint(g, n, W.rstar_obs)
         adj.append(time.perf_counter() - t)
+    # dL/da (the Kerr spin) by the checkpointed sweep: the forward states
+    # are needed, sqrt(N) of them are kept and each segment is recomputed
+    s.set_state(phi, pi)
+    torch.cuda.synchronize()
+    p0, q0 = s.phi.clone(), s.pi.clone()
+    t = time.perf_counter()
+    dLda = s.param_gradient("a", g, n, W.rstar_obs, p0, q0, h=1e-5)
+    torch.cuda.synchronize()
+    spin_s = time.perf_counter() - t
+    ck = int(np.ceil(np.sqrt(n)))
+    # (the cost does not depend on g; at r* = 300 the waveform of this run,
+    # hence g and dL/da, is zero: see the adjoint FD test for values)
+    del dLda
+    spin = {"ms": spin_s * 1e3, "over_forward": spin_s / fwd, "checkpoint_interval": ck,
+            "stored_states": int(np.ceil(n / ck)) + ck + 3}
+    del p0, q0
     # the same grid and run with an inspiralling source (mass ratio 1e-4):
     # forward with the orbit table, and the reverse sweep that also returns
     # dL/dr0 and dL/dphi of every table entry
@@ -154,6 +171,7 @@ def time_adjoint(steps=None):
             "adjoint_over_forward": min(adj) / fwd, "stored_forward_states": 0,
             "rows_per_wave": tuned[0], "steps_per_launch": tuned[1],
             "adjoint_rows_per_wave": adj_tuned[0], "adjoint_steps_per_launch": adj_tuned[1],
+            "spin_gradient": spin,
             "inspiral": {"forward_ms": fwd_m * 1e3, "adjoint_ms": min(adj_m) * 1e3,
                          "adjoint_over_forward": min(adj_m) / fwd_m, "gradient_entries": 2 * n}}
 
