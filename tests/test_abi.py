@@ -94,3 +94,50 @@ def test_suggested_dt_is_conservative(L, oracle_mod, cfg):
     mine = suggest_dt(nr, nth, r0, r1, a, 1.0, m, -2, n)
     ref = oracle_mod.stable_dt(nr, nth, r0, r1, a, 1.0, m, -2, n)
     assert 0.5 * ref < mine <= ref * (1 + 1e-12)
+
+
+def test_header_is_plain_c(tmp_path):
+    # include/teuk.h is the boundary: it must compile as C99 on its own and
+    # declare every entry point with a C prototype
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not found")
+    names = declared_functions()
+    src = tmp_path / "uses_header.c"
+    src.write_text("#include \"teuk.h\"\n"
+                   "typedef void (*entry)(void);\n"
+                   "entry entry_points[] = {\n" + ",\n".join(f"    (entry)&{n}" for n in names) + "\n};\n"
+                   "int main(void) { return entry_points[0] == 0; }\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_constants_match_header():
+    from paper_0909_4039_amd import _lib
+    src = open(HEADER).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+(TEUK_\w+)\s+\(?(-?\d+)\)?", src)}
+    want = {"TEUK_OK": _lib.OK, "TEUK_EINVAL": _lib.EINVAL, "TEUK_ESTATE": _lib.ESTATE,
+            "TEUK_EDEVICE": _lib.EDEVICE, "TEUK_EUNSTABLE": _lib.EUNSTABLE, "TEUK_ENOTSUP": _lib.ENOTSUP,
+            "TEUK_FP64": _lib.FP64, "TEUK_FP32": _lib.FP32, "TEUK_PARAM_A": _lib.PARAM_A,
+            "TEUK_PARAM_M": _lib.PARAM_M, "TEUK_PARAM_R0": _lib.PARAM_R0, "TEUK_PARAM_AMP": _lib.PARAM_AMP}
+    for k, v in want.items():
+        assert defs.get(k) == v, (k, defs.get(k), v)
+
+
+def test_null_handles_on_later_entry_points(L):
+    from paper_0909_4039_amd._lib import EINVAL
+    d = ctypes.c_double()
+    i = ctypes.c_int32()
+    assert L.teuk_set_adjoint_tiling(None, 0, 1) == EINVAL
+    assert L.teuk_get_adjoint_tiling(None, ctypes.byref(i), ctypes.byref(i)) == EINVAL
+    assert L.teuk_adjoint_autotune(None, 1, None, None) == EINVAL
+    assert L.teuk_adjoint_moving(None, 1.0, None, 1, None, 0, None, None, None, None) == EINVAL
+    assert L.teuk_param_gradient_workspace_bytes(None, 1, 0) == EINVAL
+    assert L.teuk_param_gradient(None, 0, 1e-6, 1.0, None, 1, 0.0, None, None, 0, None, 0, ctypes.byref(d),
+                                 None, None) == EINVAL
+    assert L.teuk_set_trajectory(None, None, 0) == EINVAL
+    assert L.teuk_batch_set_trajectory(None, 0, None, 0) == EINVAL
+    assert L.teuk_batch_step(None, 1) == EINVAL
