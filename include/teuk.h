@@ -21,9 +21,13 @@
  *     theta_j = (j + 1/2) pi / n_theta (cell-centred, poles excluded).
  *   - Every pointer named "device" must point to device memory of the GPU
  *     that was current at teuk_create; it stays owned by the caller.  The
- *     library allocates only its own coefficient tables (about 200 B per
- *     r* node and 64 B per theta row) at teuk_create and frees them in
- *     teuk_destroy.
+ *     library's own device memory is small and lives with the context:
+ *     its coefficient tables (about 200 B per r* node and 64 B per theta
+ *     row) from teuk_create to teuk_destroy; a batch's tables and phase
+ *     rows from teuk_batch_create to teuk_batch_destroy; and, for the
+ *     duration of one call, the trial slots of teuk_adjoint_autotune and
+ *     the two parameter-moved tables of teuk_param_gradient.  States,
+ *     waveforms and workspaces are the caller's.
  *   - Calls are asynchronous on the stream given at create unless noted.
  *   - Return value: TEUK_OK (0) or a negative TEUK_E* code.  No C++
  *     exception crosses the ABI.  A context is not thread safe; use one
