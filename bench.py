@@ -31,16 +31,26 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_0909_4039_amd", "csrc", f) for f in ("t
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_traffic.json")
 
 
+def kernel_code_hash():
+    """sha256 of the kernel sources with comments removed and whitespace
+    collapsed, so that a comment edit does not void measured counters."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        src = open(f).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(prec):
     """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they
-    were taken on the current kernel source (else None)."""
-    import hashlib
+    were taken on the current kernel code (else None)."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        h = hashlib.sha256()
-        for f in KERNEL_SRCS:
-            h.update(open(f, "rb").read())
-        if rec.get("kernel_sha256") != h.hexdigest():
+        if rec.get("kernel_code_sha256") != kernel_code_hash():
             return None
         e = rec["fp%d" % prec]
         return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],

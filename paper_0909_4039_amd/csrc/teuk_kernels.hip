@@ -91,13 +91,13 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, R gr, const Ang<R>& g
 // and one partial sum per stage are carried.
 template <typename R>
 struct Pipe {
-    cx<R> pb_prev;  // Phi mean at half point c+1/2, time n, row L-1
+    cx<R> pb_prev;  // Phi sum (twice the mean) at half point c+1/2, time n, row L-1
     cx<R> pb_acc;   // bracket of the predictor's stencil for half row L-1
-    cx<R> ph_prev;  // Phi mean at integer point c, time n+1/2, row L-2
+    cx<R> ph_prev;  // Phi sum of doubled half values (4x the mean) at c, time n+1/2, row L-2
     cx<R> ph_acc;   // bracket of the corrector's stencil for row L-2
     // Each Lax-Wendroff stage is split into its angular part, which needs the
     // next row, and the rest.  Pending (non-angular) parts:
-    cx<R> hP, hQp;  // predictor of half row L-1: final Phi, partial Pi
+    cx<R> hP, hQp;  // predictor of half row L-1, doubled: final Phi, partial Pi
     R hD;           // (dt/2) Delta/Sigma^2 at that half row
     cx<R> nQp;      // corrector of row L-2: partial Pi
     R nD;           // dt Delta/Sigma^2 at that row
@@ -142,8 +142,8 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
     const cx<R> up = st.up, uq = st.uq;
     st.up = p;
     st.uq = q;
-    // ---- A1: input row L; half-point mean and compact differences at c+1/2
-    // (rows past the grid keep a zero mean: they meet only zero weights)
+    // ---- A1: input row L; half-point sum and compact differences at c+1/2
+    // (rows past the grid keep a zero sum: they meet only zero weights)
     cx<R> pbL = zero, Qb, dP, dQ;   // Qb, dP, dQ are read only by A2, which implies A1 ran
     if (L < st.ihi) {
         cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
@@ -163,7 +163,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
         cx<R> Lf = rfma(wp, pbL, st.pb_acc);
         cx<R> hQ = rfma(st.hD, Lf, st.hQp);
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
-        phL = st.hP + hPm;       // twice twice the mean: the half-step values are doubled
+        phL = st.hP + hPm;       // four times the mean: the half-step values are doubled
         Qh = hQ + hQm;
         dhP = st.hP - hPm;
         dhQ = hQ - hQm;
