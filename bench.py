@@ -99,6 +99,30 @@ def time_solver(W, prec, steps, warmup):
     return ms, dt, kb, tiling
 
 
+def time_single_step(W, prec, steps=200, warmup=20):
+    """The same workload with one step per launch (the unblocked kernel at its
+    default tiling): milliseconds per launch, for the per-launch roofline of
+    the kernel without temporal blocking."""
+    import torch
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+    s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
+    s.set_source(W.r0, W.amp)
+    s.set_blocking(1)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rows = s.get_tiling()[0]
+    s.close()
+    return ms, rows
+
+
 def time_adjoint(steps=None):
     """Adjoint workload (a = 0.6, m = 2, 4096 x 256, 20000 steps, source r0 = 10,
     observer r* = 300): wall time of the forward run with the waveform
@@ -563,6 +587,13 @@ def main():
         "effective": {"update_bandwidth_GBs": BYTES_PER_UPDATE[64] * ups / 1e9,
                       "frac_of_hbm_peak": BYTES_PER_UPDATE[64] * ups / HBM_PEAK},
     }
+    # the kernel without temporal blocking, for comparison: one step per launch
+    ms1, rows1 = time_single_step(W, 64)
+    out["roofline"]["single_step_kernel"] = {
+        "kernel": "lw_step_kernel<double, 1>", "rows_per_wave": rows1, "launch_ms": ms1,
+        "achieved": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / 1e9,
+        "frac": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / HBM_PEAK,
+        "note": "one step per launch: slower per step than the two-step launch above, which is what runs"}
     if not args.no_fp32:
         ms32, _, kb32, _ = time_solver(W, 32, args.steps, args.warmup)
         ups32 = pts * args.steps / (ms32 * 1e-3)
