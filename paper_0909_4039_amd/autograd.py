@@ -21,6 +21,11 @@ every half step (an inspiral, the paper's Fig. 1).  Its backward pass
 (``teuk_adjoint_moving``) returns the gradient for every table row, so a
 differentiable orbit law chains through it.
 
+``waveform(..., spin=a)`` also differentiates with respect to the Kerr spin.
+The spin enters the step operator itself, so that gradient needs the
+forward states: the library keeps sqrt(N) of them and recomputes the rest
+(``teuk_param_gradient``).
+
 Gradient convention: torch's for complex tensors (for L = |z|^2 the
 gradient is 2z), which is dL/dRe + i dL/dIm, the library's convention.
 """
@@ -61,13 +66,49 @@ class TeukWaveform(torch.autograd.Function):
         solver.set_source(r0f, ampf, *sig)
         solver.set_trajectory(None)
         dphi, dpi, dr0, damp = solver.adjoint(g, n, robs, t0)
-        return (dphi, dpi, torch.tensor(dr0, dtype=ctx.r0_meta[0], device=ctx.r0_meta[1]),
-                torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]), None, None, None, None)
+        need = ctx.needs_input_grad
+        return (dphi if need[0] else None, dpi if need[1] else None,
+                torch.tensor(dr0, dtype=ctx.r0_meta[0], device=ctx.r0_meta[1]) if need[2] else None,
+                torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]) if need[3] else None,
+                None, None, None, None)
 
 
-def waveform(solver, phi0, pi0, r0, amp, n_steps, rstar_obs, t_start=0.0):
-    """Differentiable waveform w^0..w^n (see the module docstring)."""
-    return TeukWaveform.apply(phi0, pi0, r0, amp, solver, n_steps, rstar_obs, t_start)
+class TeukWaveformSpin(torch.autograd.Function):
+    """TeukWaveform with the Kerr spin as one more input.  The solver's tables
+    are built for one spin, so ``spin`` must equal the solver's a; its
+    gradient comes from the library's checkpointed parameter gradient
+    (``teuk_param_gradient``), which keeps sqrt(N) forward states, since the
+    spin enters the step operator itself."""
+
+    @staticmethod
+    def forward(ctx, phi0, pi0, r0, amp, spin, solver, n_steps, rstar_obs, t_start, h):
+        a = float(solver.params["a"])
+        if abs(float(spin) - a) > 1e-14 * max(1.0, abs(a)):
+            raise ValueError(f"spin {float(spin)!r} differs from the solver's a = {a!r}: build the solver at this spin")
+        out = TeukWaveform.forward(ctx, phi0, pi0, r0, amp, solver, n_steps, rstar_obs, t_start)
+        ctx.init = (phi0.detach().clone(), pi0.detach().clone())
+        ctx.h = h
+        ctx.spin_meta = (spin.dtype, spin.device) if torch.is_tensor(spin) else (torch.float64, phi0.device)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        dphi, dpi, dr0, damp = TeukWaveform.backward(ctx, g)[:4]
+        dspin = None
+        if ctx.needs_input_grad[4]:
+            _, _, _, n, robs, t0 = ctx.args
+            v = ctx.solver.param_gradient("a", g, n, robs, ctx.init[0], ctx.init[1], h=ctx.h, t_start=t0)
+            dspin = torch.tensor(v, dtype=ctx.spin_meta[0], device=ctx.spin_meta[1])
+        return dphi, dpi, dr0, damp, dspin, None, None, None, None, None
+
+
+def waveform(solver, phi0, pi0, r0, amp, n_steps, rstar_obs, t_start=0.0, spin=None, spin_h=1e-6):
+    """Differentiable waveform w^0..w^n (see the module docstring).  With
+    ``spin`` (equal to the solver's a) the spin is differentiable too, by the
+    checkpointed sweep (step size ``spin_h`` of its central difference)."""
+    if spin is None:
+        return TeukWaveform.apply(phi0, pi0, r0, amp, solver, n_steps, rstar_obs, t_start)
+    return TeukWaveformSpin.apply(phi0, pi0, r0, amp, spin, solver, n_steps, rstar_obs, t_start, spin_h)
 
 
 class TeukWaveformMoving(torch.autograd.Function):
@@ -109,7 +150,9 @@ class TeukWaveformMoving(torch.autograd.Function):
         dt, dev, shape = ctx.traj_meta
         full = torch.zeros(shape, dtype=torch.float64)
         full[: 2 * n] = torch.from_numpy(dtraj)
-        return (dphi, dpi, full.to(dev, dt), torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]),
+        need = ctx.needs_input_grad
+        return (dphi if need[0] else None, dpi if need[1] else None, full.to(dev, dt) if need[2] else None,
+                torch.tensor(damp, dtype=ctx.amp_meta[0], device=ctx.amp_meta[1]) if need[3] else None,
                 None, None, None)
 
 

@@ -150,3 +150,45 @@ def test_spin_gradient_full_grid_4096x256():
     print(f"[gpu] dL/da checkpointed {got:.12e} fd {fd:.12e}", flush=True)
     assert abs(fd) > 0
     assert got == pytest.approx(fd, rel=1e-5)
+
+
+def test_autograd_through_the_spin(oracle_mod):
+    # L = sum |w - target|^2; dL/dspin by autograd (checkpointed sweep) and by
+    # central differences of forward runs of solvers built at spin +- h
+    import torch
+    from paper_0909_4039_amd.autograd import waveform
+    from paper_0909_4039_amd.solver import Solver
+    c = CASE
+    dt = _dt(oracle_mod, c)
+    G, phi0, pi0 = _inputs(c, N, 106)
+    p0 = torch.as_tensor(phi0, device="cuda:0")
+    q0 = torch.as_tensor(pi0, device="cuda:0")
+    target = torch.as_tensor(G, device="cuda:0") * 1e-3
+
+    def solver_at(a):
+        s = Solver(c["nr"], c["nth"], c["rmin"], c["rmax"], a, c["M"], c["m"], c["s"], dt)
+        s.set_source(c["r0"], c["amp"])
+        return s
+
+    s = solver_at(c["a"])
+    spin = torch.tensor(c["a"], dtype=torch.float64, requires_grad=True)
+    r0 = torch.tensor(c["r0"], dtype=torch.float64, requires_grad=True)
+    w = waveform(s, p0, q0, r0, c["amp"], N, c["robs"], spin=spin, spin_h=1e-5)
+    L = torch.sum(torch.abs(w - target) ** 2)
+    L.backward()
+
+    def loss(a):
+        sa = solver_at(a)
+        with torch.no_grad():
+            v = torch.sum(torch.abs(waveform(sa, p0, q0, c["r0"], c["amp"], N, c["robs"]) - target) ** 2).item()
+        sa.close()
+        return v
+
+    h = 1e-5
+    fd = (loss(c["a"] + h) - loss(c["a"] - h)) / (2 * h)
+    print(f"[gpu] autograd dL/dspin {spin.grad.item():.12e} fd {fd:.12e}; dL/dr0 {r0.grad.item():.6e}", flush=True)
+    assert abs(fd) > 0 and r0.grad is not None
+    assert spin.grad.item() == pytest.approx(fd, rel=1e-6)
+    with pytest.raises(ValueError):
+        waveform(s, p0, q0, c["r0"], c["amp"], N, c["robs"], spin=torch.tensor(c["a"] + 0.1))
+    s.close()
