@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import FP32, FP64, TeukGrid, check
+from ._lib import FP64, TeukGrid, check
 
 
 def suggest_dt(nr, nth, rstar_min, rstar_max, a, M, m, s, n_steps) -> float:

@@ -10,7 +10,6 @@ mu = c_r + b b_* - b c_t follows from Pi = Phi_t + b Phi_* (Eq. 5).
 import math
 from fractions import Fraction
 
-import numpy as np
 import pytest
 
 sp = pytest.importorskip("sympy")

@@ -13,7 +13,6 @@ import json
 import os
 
 import numpy as np
-import pytest
 
 from paper_0909_4039_amd import inputs
 
