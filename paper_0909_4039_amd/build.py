@@ -1,4 +1,5 @@
-"""Build libteuk.so in-tree with hipcc for gfx950."""
+"""Build libteuk.so in-tree with hipcc for gfx950, and the C example that
+drives it through the C ABI alone."""
 from __future__ import annotations
 
 import os
@@ -38,5 +39,34 @@ def build(verbose: bool = False, extra_flags=None) -> str:
     return LIB
 
 
+
+
+ROOT = os.path.dirname(HERE)
+EXAMPLE_SRC = os.path.join(ROOT, "examples", "teuk_run.c")
+EXAMPLE_BIN = os.path.join(ROOT, "examples", "teuk_run")
+
+
+def build_example(verbose: bool = False, out: str = EXAMPLE_BIN) -> str:
+    """Compile examples/teuk_run.c (plain C99) against LIB and the HIP runtime
+    into out; always recompiles.  The binary finds libteuk.so next to the
+    package through its run path."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           f"-I{rocm}/include", f"-I{os.path.join(ROOT, 'include')}", EXAMPLE_SRC,
+           f"-L{HERE}", "-lteuk", f"-L{rocm}/lib", "-lamdhip64",
+           f"-Wl,-rpath,{HERE}", "-Wl,-rpath,$ORIGIN/../paper_0909_4039_amd", f"-Wl,-rpath,{rocm}/lib",
+           "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("gcc failed building examples/teuk_run")
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_example(verbose=True))

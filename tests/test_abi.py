@@ -3,6 +3,8 @@ declares, validates arguments, and its host geometry agrees with the oracle."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -99,8 +101,6 @@ def test_suggested_dt_is_conservative(L, oracle_mod, cfg):
 def test_header_is_plain_c(tmp_path):
     # include/teuk.h is the boundary: it must compile as C99 on its own and
     # declare every entry point with a C prototype
-    import shutil
-    import subprocess
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("gcc not found")
@@ -141,3 +141,14 @@ def test_null_handles_on_later_entry_points(L):
     assert L.teuk_set_trajectory(None, None, 0) == EINVAL
     assert L.teuk_batch_set_trajectory(None, 0, None, 0) == EINVAL
     assert L.teuk_batch_step(None, 1) == EINVAL
+
+
+def test_c_example_builds_and_prints_usage(tmp_path):
+    # examples/teuk_run.c is plain C99 over the header and the library; with
+    # no arguments it prints its usage before any HIP call
+    from paper_0909_4039_amd import build as B
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    exe = B.build_example(out=str(tmp_path / "teuk_run"))
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage:" in r.stderr
