@@ -370,7 +370,29 @@ const char* teuk_batch_last_error(teuk_batch* b);
  * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */
 int teuk_check_finite(teuk_ctx* ctx);
 
-/* Sticky status of the context (TEUK_OK if no call has failed). */
+/* Watchdog for long runs.  The explicit scheme of Eqs. (13)-(14) is stable
+ * only while the time step and the grid keep every mode damped; where they
+ * do not (a time step far below dr*, a source a few cells wide) a poorly
+ * resolved mode can grow without bound.  With every_steps > 0, teuk_step
+ * scans the state (Phi and Pi, real and imaginary parts) whenever the step
+ * count reaches a multiple of every_steps, for a value whose magnitude is
+ * not below max_abs (max_abs <= 0: for non-finite values only).  Launches
+ * are split so that each multiple is a launch boundary (results stay
+ * bitwise identical; each scan reads the state once).  The scans run on the
+ * context's stream and teuk_step stays asynchronous: each call ends by
+ * copying the finding into host memory, and the first later teuk_step,
+ * teuk_status or teuk_check_finite that sees it sets the sticky
+ * TEUK_EUNSTABLE, with the step of the first failing scan in
+ * teuk_last_error.  After a stream synchronisation, teuk_status reports
+ * every scan of the calls made so far.  every_steps = 0 (the default)
+ * turns the watchdog off; a call clears earlier findings (it synchronises
+ * the stream).  TEUK_EINVAL for every_steps < 0 or max_abs NaN; allocates
+ * 8 B of device memory and 8 B of pinned host memory on first use, kept
+ * until teuk_destroy. */
+int teuk_set_watchdog(teuk_ctx* ctx, int64_t every_steps, double max_abs);
+
+/* Sticky status of the context (TEUK_OK if no call has failed), including
+ * a watchdog finding that has reached the host. */
 int teuk_status(teuk_ctx* ctx);
 
 /* Text of the last failure of this context ("" if none). */

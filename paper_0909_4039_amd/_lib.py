@@ -78,6 +78,7 @@ _SIGS = {
     "teuk_batch_status": (ctypes.c_int, [_P]),
     "teuk_batch_last_error": (ctypes.c_char_p, [_P]),
     "teuk_check_finite": (ctypes.c_int, [_P]),
+    "teuk_set_watchdog": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double]),
     "teuk_status": (ctypes.c_int, [_P]),
     "teuk_last_error": (ctypes.c_char_p, [_P]),
     "teuk_strerror": (ctypes.c_char_p, [ctypes.c_int]),

@@ -49,6 +49,14 @@ struct teuk_ctx {
     // tiling of the reverse sweep: adj_rows 0 follows the forward's rows
     int adj_rows = 0;
     int adj_kb = 1;
+    // watchdog: scan the state every watch_every steps (0: off); d_watch
+    // holds step + 1 of the first scan that found a value at or above
+    // watch_lim, and each teuk_step ends with a copy of it into the pinned
+    // host word h_watch, read without waiting by later calls
+    int64_t watch_every = 0;
+    double watch_lim = 0;
+    unsigned long long* d_watch = nullptr;
+    volatile unsigned long long* h_watch = nullptr;
     // errors
     int status = TEUK_OK;
     char err[512] = {0};
@@ -74,6 +82,15 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
     } while (0)
 
 size_t elem_size(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
+
+// Turn a watchdog finding that has reached the host into the sticky
+// TEUK_EUNSTABLE (no wait: a scan still in flight is seen by a later call).
+int watch_poll(teuk_ctx* c) {
+    if (c->status == TEUK_OK && c->h_watch && *c->h_watch != 0ull)
+        return fail(c, TEUK_EUNSTABLE, "watchdog: a value not below %g in magnitude (or not finite) at step %lld",
+                    c->watch_lim, (long long)(*c->h_watch - 1));
+    return c->status;
+}
 
 int upload_tables(teuk_ctx* c) {
     const Geometry& g = c->geo;
@@ -161,18 +178,42 @@ int launch_one(teuk_ctx* c, StepArgs<R>& a, int kb, int src, int64_t step, bool 
     return TEUK_OK;
 }
 
+// Watchdog scan of the current state (both fields), tagged with the step.
+template <typename R>
+int launch_watch(teuk_ctx* c) {
+    const int64_t n = 2 * c->geo.nr * c->geo.nth;
+    for (int f = 0; f < 2; ++f) {
+        if constexpr (std::is_same<R, double>::value)
+            launch_watch_fp64((const double*)c->buf[c->cur][f], n, c->watch_lim, c->step, c->d_watch, c->stream);
+        else
+            launch_watch_fp32((const float*)c->buf[c->cur][f], n, (float)c->watch_lim, c->step, c->d_watch,
+                              c->stream);
+        HIP_TRY(c, hipGetLastError());
+    }
+    return TEUK_OK;
+}
+
 template <typename R>
 int launch_steps(teuk_ctx* c, int64_t n) {
     const Geometry& g = c->geo;
     StepArgs<R> a = step_args<R>(c);
     for (int64_t done = 0; done < n;) {
-        const int kb = (c->kblock >= 2 && n - done >= 2) ? 2 : 1;
+        // with the watchdog on, a launch never crosses a multiple of watch_every
+        int kb = (c->kblock >= 2 && n - done >= 2) ? 2 : 1;
+        if (c->watch_every > 0 && kb == 2 && (c->step + 1) % c->watch_every == 0) kb = 1;
         int rc = launch_one<R>(c, a, kb, c->cur, c->step, true);
         if (rc != TEUK_OK) return rc;
         c->cur = 1 - c->cur;
         c->step += kb;
         done += kb;
+        if (c->watch_every > 0 && c->step % c->watch_every == 0) {
+            rc = launch_watch<R>(c);
+            if (rc != TEUK_OK) return rc;
+        }
     }
+    if (c->watch_every > 0 && n > 0)
+        HIP_TRY(c, hipMemcpyAsync((void*)c->h_watch, c->d_watch, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                  c->stream));
     // the last state's waveform row
     int64_t row = c->step - c->obs_step0;
     if (c->wave && row >= 0 && row < c->wave_cap) {
@@ -495,11 +536,13 @@ int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, do
 
 int teuk_destroy(teuk_ctx* c) {
     if (!c) return TEUK_EINVAL;
-    if (c->d_rad_i || c->d_rad_h || c->d_ang || c->d_flag) (void)hipStreamSynchronize(c->stream);
+    if (c->d_rad_i || c->d_rad_h || c->d_ang || c->d_flag || c->d_watch) (void)hipStreamSynchronize(c->stream);
     if (c->d_rad_i) (void)hipFree(c->d_rad_i);
     if (c->d_rad_h) (void)hipFree(c->d_rad_h);
     if (c->d_ang) (void)hipFree(c->d_ang);
     if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->d_watch) (void)hipFree(c->d_watch);
+    if (c->h_watch) (void)hipHostFree((void*)c->h_watch);
     delete c;
     return TEUK_OK;
 }
@@ -596,7 +639,7 @@ int teuk_set_observer(teuk_ctx* c, double rstar_obs, void* wave, int64_t capacit
 
 static int teuk_step_impl(teuk_ctx* c, int64_t n) {
     if (!c) return TEUK_EINVAL;
-    if (c->status != TEUK_OK) return c->status;
+    if (watch_poll(c) != TEUK_OK) return c->status;
     if (n < 0) return fail(c, TEUK_EINVAL, "negative step count");
     if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
     if (n == 0 && !c->wave) return TEUK_OK;
@@ -1176,7 +1219,7 @@ int teuk_param_gradient(teuk_ctx* c, int32_t param, double h, double rstar_obs, 
 
 int teuk_check_finite(teuk_ctx* c) {
     if (!c) return TEUK_EINVAL;
-    if (c->status != TEUK_OK) return c->status;
+    if (watch_poll(c) != TEUK_OK) return c->status;
     if (!c->bound) return fail(c, TEUK_ESTATE, "no state bound");
     unsigned int zero = 0, flag = 0;
     HIP_TRY(c, hipMemcpyAsync(c->d_flag, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
@@ -1192,7 +1235,31 @@ int teuk_check_finite(teuk_ctx* c) {
     return TEUK_OK;
 }
 
-int teuk_status(teuk_ctx* c) { return c ? c->status : TEUK_EINVAL; }
+int teuk_status(teuk_ctx* c) { return c ? watch_poll(c) : TEUK_EINVAL; }
+
+int teuk_set_watchdog(teuk_ctx* c, int64_t every_steps, double max_abs) {
+    if (!c) return TEUK_EINVAL;
+    if (every_steps < 0) return fail(c, TEUK_EINVAL, "negative watchdog interval");
+    if (std::isnan(max_abs)) return fail(c, TEUK_EINVAL, "watchdog bound is NaN");
+    if (c->status != TEUK_OK) return c->status;
+    if (every_steps > 0 && !c->d_watch) {
+        HIP_TRY(c, hipMalloc((void**)&c->d_watch, sizeof(unsigned long long)));
+        void* h = nullptr;
+        HIP_TRY(c, hipHostMalloc(&h, sizeof(unsigned long long), hipHostMallocDefault));
+        c->h_watch = (volatile unsigned long long*)h;
+    }
+    if (c->d_watch) {
+        // drop earlier findings: no copy into h_watch is in flight after the wait
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        launch_fill_zero((double*)c->d_watch, 1, c->stream);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        *c->h_watch = 0ull;
+    }
+    c->watch_every = every_steps;
+    c->watch_lim = max_abs > 0.0 ? max_abs : HUGE_VAL;
+    return TEUK_OK;
+}
 
 const char* teuk_last_error(teuk_ctx* c) { return c ? c->err : "null context"; }
 

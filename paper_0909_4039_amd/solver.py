@@ -277,6 +277,12 @@ class Solver:
         """Raise TeukError(EUNSTABLE) if the state holds NaN or Inf."""
         check(_lib.lib().teuk_check_finite(self._ctx), self._ctx)
 
+    def set_watchdog(self, every_steps, max_abs=0.0):
+        """Scan the state every ``every_steps`` steps during ``step`` for values
+        not below ``max_abs`` in magnitude (0: non-finite only); a finding makes
+        later calls raise TeukError(EUNSTABLE).  0 turns it off."""
+        check(_lib.lib().teuk_set_watchdog(self._ctx, int(every_steps), float(max_abs)), self._ctx)
+
     def status(self):
         return _lib.lib().teuk_status(self._ctx)
 
