@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libteuk.so")
-SOURCES = ["teuk_api.cpp", "teuk_geom.cpp", "teuk_batch.cpp", "teuk_kernels.hip", "teuk_adjoint.hip"]
+SOURCES = ["teuk_api.cpp", "teuk_geom.cpp", "teuk_batch.cpp", "teuk_kernels.hip", "teuk_adjoint.hip",
+           "teuk_watch.hip"]
 ARCH = os.environ.get("TEUK_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
