@@ -542,7 +542,7 @@ def cpu_baseline(W, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); libteuk has no multi-GPU "
               "path", file=sys.stderr)
         sys.exit(2)
     from paper_0909_4039_amd import workloads

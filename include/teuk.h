@@ -49,7 +49,7 @@ extern "C" {
 #define TEUK_EDEVICE (-3)   /* a HIP call or a host allocation failed; teuk_last_error has the text.
                                No C++ exception leaves any entry point. */
 #define TEUK_EUNSTABLE (-4) /* non-finite values found in the state            */
-#define TEUK_ENOTSUP (-5)   /* valid request this build does not serve         */
+#define TEUK_ENOTSUP (-5)   /* valid request the library does not serve        */
 
 #define TEUK_FP64 64
 #define TEUK_FP32 32
