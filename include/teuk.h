@@ -366,6 +366,18 @@ int teuk_batch_get_step(teuk_batch* b, int64_t* step);
 int teuk_batch_status(teuk_batch* b);
 const char* teuk_batch_last_error(teuk_batch* b);
 
+/* Watchdog of a batch (see teuk_set_watchdog): with on != 0, every
+ * teuk_batch_step call ends with a scan of each instance's state for a
+ * value not below max_abs in magnitude (max_abs <= 0: non-finite only);
+ * graph replays are not split, so the scans follow the calls, not a step
+ * interval.  The finding (instance and step) reaches the host without a
+ * wait; the next teuk_batch_step or teuk_batch_status turns it into the
+ * sticky TEUK_EUNSTABLE, named in teuk_batch_last_error.  A call clears
+ * earlier findings (it synchronises the stream); TEUK_EINVAL for max_abs
+ * NaN.  Allocates 8 B of device and 8 B of pinned host memory on first use,
+ * kept until teuk_batch_destroy. */
+int teuk_batch_set_watchdog(teuk_batch* b, int32_t on, double max_abs);
+
 /* Scan the current state for non-finite values (synchronous).  Returns
  * TEUK_OK, TEUK_EUNSTABLE, or the sticky error of an earlier failure. */
 int teuk_check_finite(teuk_ctx* ctx);

@@ -77,6 +77,7 @@ _SIGS = {
     "teuk_batch_get_step": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "teuk_batch_status": (ctypes.c_int, [_P]),
     "teuk_batch_last_error": (ctypes.c_char_p, [_P]),
+    "teuk_batch_set_watchdog": (ctypes.c_int, [_P, _I32, ctypes.c_double]),
     "teuk_check_finite": (ctypes.c_int, [_P]),
     "teuk_set_watchdog": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double]),
     "teuk_status": (ctypes.c_int, [_P]),

@@ -116,6 +116,15 @@ class Batch:
         _check(_lib.lib().teuk_batch_get_step(self._b, ctypes.byref(v)), self._b)
         return v.value
 
+    def set_watchdog(self, on=True, max_abs=0.0):
+        """End every ``step`` with a scan of each instance for values not below
+        ``max_abs`` in magnitude (0: non-finite only); a finding makes later
+        calls raise TeukError(EUNSTABLE)."""
+        _check(_lib.lib().teuk_batch_set_watchdog(self._b, int(bool(on)), float(max_abs)), self._b)
+
+    def status(self):
+        return _lib.lib().teuk_batch_status(self._b)
+
     def synchronize(self):
         self.stream.synchronize()
 

@@ -38,6 +38,13 @@ struct teuk_batch {
     bool dirty = true;                  // descriptors changed since the last upload
     hipGraphExec_t graph = nullptr;
     int graph_launches = 0;             // launches of kblock steps per replay
+    // watchdog: every teuk_batch_step ends with a scan of each bound
+    // instance; d_watch keeps (instance << 40 | step) + 1 of the first
+    // finding and is copied into the pinned word h_watch
+    bool watch_on = false;
+    double watch_lim = 0;
+    unsigned long long* d_watch = nullptr;
+    volatile unsigned long long* h_watch = nullptr;
     int status = TEUK_OK;
     char err[512] = {0};
 };
@@ -50,7 +57,7 @@ int bfail(teuk_batch* b, int code, const char* fmt, ...) {
         va_start(ap, fmt);
         std::vsnprintf(b->err, sizeof(b->err), fmt, ap);
         va_end(ap);
-        if (code == TEUK_EDEVICE) b->status = code;
+        if (code == TEUK_EDEVICE || code == TEUK_EUNSTABLE) b->status = code;
     }
     return code;
 }
@@ -60,6 +67,20 @@ int bfail(teuk_batch* b, int code, const char* fmt, ...) {
         hipError_t e_ = (expr);                                                                          \
         if (e_ != hipSuccess) return bfail((b), TEUK_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+constexpr int WATCH_SHIFT = 40;   // steps below 2^40 in a watchdog label
+
+// Turn a watchdog finding that has reached the host into the sticky
+// TEUK_EUNSTABLE (no wait).
+int watch_poll(teuk_batch* b) {
+    if (b->status == TEUK_OK && b->h_watch && *b->h_watch != 0ull) {
+        const unsigned long long v = *b->h_watch - 1;
+        return bfail(b, TEUK_EUNSTABLE,
+                     "watchdog: instance %llu has a value not below %g in magnitude (or not finite) at step %llu",
+                     v >> WATCH_SHIFT, b->watch_lim, v & ((1ull << WATCH_SHIFT) - 1));
+    }
+    return b->status;
+}
 
 int dev_copy(teuk_batch* b, void** dst, const void* src, size_t bytes) {
     b->allocs.reserve(b->allocs.size() + 1);  // a failed push_back must not lose the device block
@@ -308,6 +329,8 @@ int teuk_batch_destroy(teuk_batch* b) {
     for (void* p : b->allocs) (void)hipFree(p);
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_clock) (void)hipFree(b->d_clock);
+    if (b->d_watch) (void)hipFree(b->d_watch);
+    if (b->h_watch) (void)hipHostFree((void*)b->h_watch);
     delete b;
     return TEUK_OK;
 }
@@ -340,6 +363,7 @@ int teuk_batch_bind(teuk_batch* b, int32_t i, void* phi, void* pi, void* phi_nex
 
 int teuk_batch_step(teuk_batch* b, int64_t n) {
     if (!b) return TEUK_EINVAL;
+    if (watch_poll(b) != TEUK_OK) return b->status;
     if (n < 0) return bfail(b, TEUK_EINVAL, "negative step count");
     int rc = ready(b);
     if (rc != TEUK_OK) return rc;
@@ -373,6 +397,41 @@ int teuk_batch_step(teuk_batch* b, int64_t n) {
     for (const Geometry& g : b->geo) max_nth = std::max<int>(max_nth, (int)g.nth);
     launch_batch_extract(b->d_inst, b->n, max_nth, b->d_clock, b->stream);
     BHIP(b, hipGetLastError());
+    if (b->watch_on && n > 0) {
+        const int cur = (int)(b->launches & 1);
+        for (int i = 0; i < b->n; ++i) {
+            const int64_t npts = 2 * b->geo[i].nr * b->geo[i].nth;
+            const int64_t tag = ((int64_t)i << WATCH_SHIFT) | (b->step & ((1ll << WATCH_SHIFT) - 1));
+            for (int f = 0; f < 2; ++f) {
+                launch_watch_fp64(b->inst[i].buf[cur][f], npts, b->watch_lim, tag, b->d_watch, b->stream);
+                BHIP(b, hipGetLastError());
+            }
+        }
+        BHIP(b, hipMemcpyAsync((void*)b->h_watch, b->d_watch, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               b->stream));
+    }
+    return TEUK_OK;
+}
+
+int teuk_batch_set_watchdog(teuk_batch* b, int32_t on, double max_abs) {
+    if (!b) return TEUK_EINVAL;
+    if (std::isnan(max_abs)) return bfail(b, TEUK_EINVAL, "watchdog bound is NaN");
+    if (b->status != TEUK_OK) return b->status;
+    if (on && !b->d_watch) {
+        BHIP(b, hipMalloc((void**)&b->d_watch, sizeof(unsigned long long)));
+        void* h = nullptr;
+        BHIP(b, hipHostMalloc(&h, sizeof(unsigned long long), hipHostMallocDefault));
+        b->h_watch = (volatile unsigned long long*)h;
+    }
+    if (b->d_watch) {
+        BHIP(b, hipStreamSynchronize(b->stream));
+        launch_fill_zero((double*)b->d_watch, 1, b->stream);
+        BHIP(b, hipGetLastError());
+        BHIP(b, hipStreamSynchronize(b->stream));
+        *b->h_watch = 0ull;
+    }
+    b->watch_on = on != 0;
+    b->watch_lim = max_abs > 0.0 ? max_abs : HUGE_VAL;
     return TEUK_OK;
 }
 
@@ -543,7 +602,7 @@ int teuk_batch_get_step(teuk_batch* b, int64_t* step) {
     return TEUK_OK;
 }
 
-int teuk_batch_status(teuk_batch* b) { return b ? b->status : TEUK_EINVAL; }
+int teuk_batch_status(teuk_batch* b) { return b ? watch_poll(b) : TEUK_EINVAL; }
 
 const char* teuk_batch_last_error(teuk_batch* b) { return b ? b->err : "null batch"; }
 

@@ -218,9 +218,9 @@ void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_
 void launch_param_dot(const double* lp, const double* lq, const double* pp, const double* pq, const double* mp,
                       const double* mq, int64_t n_real, double* part, double* out, hipStream_t s);
 int param_dot_parts();
-void launch_watch_fp64(const double* x, int64_t n, double lim, int64_t step, unsigned long long* found,
+void launch_watch_fp64(const double* x, int64_t n, double lim, int64_t tag, unsigned long long* found,
                        hipStream_t s);
-void launch_watch_fp32(const float* x, int64_t n, float lim, int64_t step, unsigned long long* found,
+void launch_watch_fp32(const float* x, int64_t n, float lim, int64_t tag, unsigned long long* found,
                        hipStream_t s);
 void launch_count_nonfinite_fp64(const double* x, int64_t n, unsigned int* flag, hipStream_t s);
 void launch_count_nonfinite_fp32(const float* x, int64_t n, unsigned int* flag, hipStream_t s);

@@ -141,6 +141,7 @@ def test_null_handles_on_later_entry_points(L):
     assert L.teuk_set_trajectory(None, None, 0) == EINVAL
     assert L.teuk_batch_set_trajectory(None, 0, None, 0) == EINVAL
     assert L.teuk_set_watchdog(None, 10, 1.0) == EINVAL
+    assert L.teuk_batch_set_watchdog(None, 1, 1.0) == EINVAL
     assert L.teuk_batch_step(None, 1) == EINVAL
 
 

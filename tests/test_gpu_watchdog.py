@@ -131,3 +131,42 @@ def test_watchdog_catches_the_growing_mode(nr, nth, trips):
     else:
         assert status == _lib.OK
     sol.close()
+
+
+def test_batch_watchdog_names_the_instance():
+    import torch
+    from paper_0909_4039_amd import batch as B
+    from paper_0909_4039_amd.solver import suggest_dt
+    descs = []
+    for m, (nr, nth) in zip((1, 2, 3), ((160, 24), (200, 33), (140, 20))):
+        dt = suggest_dt(nr, nth, -60.0, 140.0, 0.5, 1.0, m, -2, 200)
+        descs.append(B.make_desc(nr, nth, -60.0, 140.0, 0.5, m, dt, r0=9.0, amp=1.0, rstar_obs=60.0))
+    states = [inputs.random_state(d.grid.n_rstar, d.grid.n_theta, 20 + i) for i, d in enumerate(descs)]
+    # reference: no watchdog
+    ref = B.Batch(descs, 40)
+    for i, (p, q) in enumerate(states):
+        ref.set_state(i, p, q)
+    ref.step(10)
+    torch.cuda.synchronize()
+    want = [ref.phi(i).cpu().numpy() for i in range(3)]
+    ref.close()
+    bt = B.Batch(descs, 40)
+    for i, (p, q) in enumerate(states):
+        bt.set_state(i, p, q)
+    bt.set_watchdog(True, 1e30)
+    bt.step(10)
+    torch.cuda.synchronize()
+    assert bt.status() == _lib.OK
+    for i in range(3):
+        assert np.array_equal(bt.phi(i).cpu().numpy(), want[i])
+    # a NaN written into instance 1 is named with the step of the scan
+    p1 = bt.phi(1)
+    p1[5, 50] = float("nan")
+    torch.cuda.synchronize()
+    bt.step(4)
+    torch.cuda.synchronize()
+    with pytest.raises(_lib.TeukError) as e:
+        bt.step(1)
+    assert e.value.code == _lib.EUNSTABLE
+    assert "instance 1" in str(e.value) and "at step 14" in str(e.value), str(e.value)
+    bt.close()
