@@ -79,6 +79,32 @@ class Solver:
             self.phi.copy_(torch.as_tensor(phi).to(self.device, self.dtype))
             self.pi.copy_(torch.as_tensor(pi).to(self.device, self.dtype))
 
+    def state_dict(self):
+        """A checkpoint from which a fresh Solver of the same grid, mode, dt and
+        precision continues this run bit for bit: host copies of the current
+        state, the time and step count, the source, and the part of the orbit
+        table not used yet.  Tensors and plain Python values only, so
+        ``torch.save`` / ``torch.load(weights_only=True)`` round-trip it."""
+        self.stream.synchronize()
+        t, step = self.get_time()
+        d = {"params": dict(self.params, prec=self.prec), "phi": self.phi.cpu(), "pi": self.pi.cpu(),
+             "t": t, "step": step, "source": self.source, "trajectory": None}
+        if self.trajectory is not None:
+            d["trajectory"] = torch.from_numpy(self.trajectory[2 * (step - self._traj_step0):].copy())
+        return d
+
+    def load_state_dict(self, d):
+        """Continue from a ``state_dict`` of a run with the same grid, mode, dt
+        and precision (ValueError otherwise).  The observer is not part of it."""
+        mine = dict(self.params, prec=self.prec)
+        if {k: d["params"].get(k) for k in mine} != mine:
+            raise ValueError(f"checkpoint of {d['params']} does not match this solver {mine}")
+        self.set_state(d["phi"], d["pi"])
+        self.set_time(d["t"], d["step"])
+        if d["source"] is not None:
+            self.set_source(*d["source"])
+        self.set_trajectory(None if d["trajectory"] is None else d["trajectory"].numpy())
+
     # ------------------------------------------------------------ physics
     def set_source(self, r0, amp, sigma_r_cells=2.0, sigma_th_cells=2.0):
         check(_lib.lib().teuk_set_source(self._ctx, r0, amp, sigma_r_cells, sigma_th_cells), self._ctx)
@@ -97,6 +123,7 @@ class Solver:
         check(_lib.lib().teuk_set_trajectory(self._ctx, tab.ctypes.data_as(ctypes.c_void_p), tab.shape[0]),
               self._ctx)
         self.trajectory = tab
+        self._traj_step0 = self.get_time()[1]
 
     def set_observer(self, rstar_obs, capacity_rows):
         """Record the waveform at rstar_obs into a new (capacity_rows, n_theta) tensor."""
