@@ -165,14 +165,26 @@ class Solver:
     def get_blocking(self):
         return check_int(_lib.lib().teuk_get_blocking(self._ctx))
 
-    def autotune(self, launches_per_trial=20):
+    def autotune(self, launches_per_trial=20, cache=None):
         """Pick the fastest (theta rows per wave, steps per launch) by timing
         trial launches on the bound state; returns (rows, steps_per_launch).
-        Results of ``step`` are bitwise identical for every choice."""
+        Results of ``step`` are bitwise identical for every choice.  With a
+        cache file (``cache`` or the TEUK_TUNE_CACHE environment variable) a
+        choice found earlier for this grid, precision and GPU model is applied
+        without trials, and a new one is recorded."""
+        from . import tune_cache
+        path = tune_cache.cache_path(cache)
+        k_ = tune_cache.key(torch.cuda.get_device_name(self.device), self.prec, self.shape, "step")
+        hit = tune_cache.lookup(path, k_)
+        if hit is not None and len(hit) == 2:
+            self.set_tiling(hit[0], 0)
+            self.set_blocking(hit[1])
+            return hit[0], hit[1]
         r = ctypes.c_int32()
         k = ctypes.c_int32()
         check(_lib.lib().teuk_autotune(self._ctx, int(launches_per_trial), ctypes.byref(r), ctypes.byref(k)),
               self._ctx)
+        tune_cache.store(path, k_, (r.value, k.value))
         return r.value, k.value
 
     def get_tiling(self):

@@ -54,3 +54,22 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral):
         c.load_state_dict(torch.load(tmp_path / "ckpt.pt", weights_only=True))
     b.close()
     c.close()
+
+
+def test_autotune_cache_reuses_a_choice(tmp_path):
+    import torch
+    from paper_0909_4039_amd import tune_cache
+    from paper_0909_4039_amd.solver import suggest_dt
+    dt = suggest_dt(NR, NTH, RMIN, RMAX, A, M, MM, S, 1000)
+    path = str(tmp_path / "tune.json")
+    a = make(dt)
+    choice = a.autotune(3, cache=path)
+    a.close()
+    k = tune_cache.key(torch.cuda.get_device_name(0), 64, (NTH, NR), "step")
+    assert tune_cache.lookup(path, k) == list(choice)
+    # a planted entry is applied as it is, without trials
+    tune_cache.store(path, k, (5, 1))
+    b = make(dt)
+    assert b.autotune(3, cache=path) == (5, 1)
+    assert b.get_tiling()[0] == 5 and b.get_blocking() == 1
+    b.close()
