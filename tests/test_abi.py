@@ -115,6 +115,20 @@ def test_header_is_plain_c(tmp_path):
     assert r.returncode == 0, r.stderr
 
 
+def test_header_compiles_as_cpp(tmp_path):
+    # the same header from C++: extern "C" linkage, no C-only constructs
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    src = tmp_path / "uses_header.cpp"
+    src.write_text("#include \"teuk.h\"\n"
+                   "static_assert(sizeof(teuk_grid) == 32, \"teuk_grid layout\");\n"
+                   "int main() { return teuk_strerror(TEUK_OK) == nullptr; }\n")
+    r = subprocess.run([gxx, "-std=c++17", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_constants_match_header():
     from paper_0909_4039_amd import _lib
     src = open(HEADER).read()
