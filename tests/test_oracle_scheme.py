@@ -153,3 +153,35 @@ def test_window_domain_of_dependence(oracle_mod):
         jlo = 0 if j0 == 0 else 2 * n
         jhi = nj if j0 + nj == nth else nj - 2 * n
         assert ok[jlo:jhi, ilo:ihi].all()
+
+
+def _peak_after(oracle_mod, nr, T, dt_scale=1.0, nth=16):
+    """max |Phi| at time T of the s = -2, m = 2, a = 0 pulse run used by the
+    ringdown pins (l = 2 profile, pulse at r* = 20, r* in [-100, 300])."""
+    rmin, rmax = -100.0, 300.0
+    A = oracle_mod.angular_matrix(nth, 2, -2)
+    ev, V = np.linalg.eig(A)
+    Y = np.real(V[:, np.argmin(np.abs(ev + 4.0))])
+    Y /= Y[np.argmax(np.abs(Y))]
+    dt = dt_scale * oracle_mod.stable_dt(nr, nth, rmin, rmax, 0.0, 1.0, 2, -2, 20000)
+    rs, _ = inputs.grid(nr, nth, rmin, rmax)
+    g = np.exp(-(rs - 20.0) ** 2 / 32.0)
+    phi = (Y[:, None] * g[None, :]).astype(complex)
+    pi = (Y[:, None] * (-(rs - 20.0) / 16.0 * g)[None, :]).astype(complex)
+    o = oracle_mod.Oracle(nr, nth, rmin, rmax, 0.0, 1.0, 2, -2, dt, rstar_obs=40.0)
+    p, _, _ = o.run(phi, pi, int(round(T / dt)), record=False)
+    return float(np.abs(p).max())
+
+
+def test_poorly_resolved_mode_follows_the_courant_number(oracle_mod):
+    """Lax-Wendroff damps wavelengths of a few cells at a rate that scales as
+    (dt/dr*)^2.  With dt set by the theta operator, dt/dr* is small on coarse
+    r* grids and a mode at the potential peak grows (the field starts at 1
+    and the outgoing pulse stays near 150); a smaller dt makes it grow faster,
+    and a finer r* grid (larger dt/dr*) removes it over the same time."""
+    coarse = _peak_after(oracle_mod, 257, 150.0)
+    coarse_half_dt = _peak_after(oracle_mod, 257, 150.0, dt_scale=0.5)
+    fine = _peak_after(oracle_mod, 1025, 150.0)
+    assert coarse > 1e5, coarse
+    assert coarse_half_dt > 1.1 * coarse, (coarse_half_dt, coarse)
+    assert fine < 200.0, fine
