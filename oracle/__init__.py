@@ -21,11 +21,11 @@ _SRC = os.path.join(_HERE, "teuk_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Kerr (a != 0) pointwise field values have no printed value to compare
-# with.  They are pinned indirectly: by the a = 0.5, l = m = 2 ringdown
-# frequency (tests/golden, Leaver's value), which depends on every
-# a-dependent coefficient, and by the invariants (convergence order, mirror
-# symmetry, linearity, a -> 0 continuity, adjoint identity).  No function of
-# the oracle is left without a pin.
+# with.  They are pinned indirectly: by the l = m = 2 ringdown frequencies at
+# a = 0.5, 0.9 and 0.99 (tests/golden, Leaver's values), which depend on
+# every a-dependent coefficient, and by the invariants (convergence order,
+# mirror symmetry, linearity, a -> 0 continuity, adjoint identity).  No
+# function of the oracle is left without a pin.
 PARITY_UNPINNED = ()
 
 
