@@ -60,6 +60,9 @@ SMALL = [
     dict(name="odd_s_129x8", nr=129, nth=8, rmin=-40.0, rmax=90.0, a=0.5, m=0, s=-1, robs=0.0, n=50),
     dict(name="m8_300x37", nr=300, nth=37, rmin=-100.0, rmax=400.0, a=0.9, m=8, s=-2, robs=300.0,
          r0=11.0, amp=1.0, n=40),
+    dict(name="s0_97x12", nr=97, nth=12, rmin=-40.0, rmax=80.0, a=0.7, m=1, s=0, robs=20.0, r0=8.0, amp=1.0,
+         n=40),
+    dict(name="s+1_111x10", nr=111, nth=10, rmin=-40.0, rmax=80.0, a=0.4, m=2, s=1, robs=30.0, n=40),
 ]
 
 
