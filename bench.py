@@ -70,7 +70,7 @@ def parse():
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-others", action="store_true")
     p.add_argument("--no-copy", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
     return p.parse_args()
 
 
