@@ -14,19 +14,20 @@ pytestmark = pytest.mark.gpu
 NR, NTH, RMIN, RMAX, A, M, MM, S = 190, 37, -60.0, 140.0, 0.9, 1.0, 2, -2
 
 
-def make(dt):
+def make(dt, prec=64):
     from paper_0909_4039_amd.solver import Solver
-    return Solver(NR, NTH, RMIN, RMAX, A, M, MM, S, dt)
+    return Solver(NR, NTH, RMIN, RMAX, A, M, MM, S, dt, prec=prec)
 
 
-@pytest.mark.parametrize("inspiral", [False, True], ids=["fixed_orbit", "inspiral"])
-def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral):
+@pytest.mark.parametrize("inspiral,prec", [(False, 64), (True, 64), (True, 32)],
+                         ids=["fixed_orbit", "inspiral", "inspiral_fp32"])
+def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral, prec):
     import torch
     from paper_0909_4039_amd.solver import suggest_dt
     n = 30
     dt = suggest_dt(NR, NTH, RMIN, RMAX, A, M, MM, S, 1000)
     phi, pi = inputs.random_state(NR, NTH, 31)
-    a = make(dt)
+    a = make(dt, prec)
     a.set_source(9.0, 1.0)
     if inspiral:
         a.set_trajectory(inputs.inspiral_trajectory(9.0, A, M, 0.05, dt, 2 * n))
@@ -39,7 +40,7 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral):
     want = (a.phi.cpu().numpy(), a.pi.cpu().numpy(), a.wave.cpu().numpy(), a.get_time())
     a.close()
 
-    b = make(dt)
+    b = make(dt, prec)
     b.load_state_dict(torch.load(tmp_path / "ckpt.pt", weights_only=True))
     b.set_observer(60.0, n + 1)
     b.step(n)
@@ -49,7 +50,7 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral):
         assert np.array_equal(x, y)
     assert got[3] == want[3]
     # a checkpoint of another run does not load
-    c = make(dt * 0.5)
+    c = make(dt, 96 - prec)                       # the other precision
     with pytest.raises(ValueError):
         c.load_state_dict(torch.load(tmp_path / "ckpt.pt", weights_only=True))
     b.close()
