@@ -301,3 +301,32 @@ def test_fp32_waveform_error_kerr_8192x256(oracle_mod):
     err_w = rel(gw, ow)
     print(f"[gpu] fp32 8192x256 waveform rel err {err_w:.3e}, state {rel(gp, op):.3e}", flush=True)
     assert err_w <= 1e-5, err_w
+
+
+def _random_cases(k=16, seed=2027):
+    """Seeded random grids, spins, modes, sources, tilings and blocking, all
+    within the documented limits."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        rmin, rmax = float(rng.uniform(-80.0, -10.0)), float(rng.uniform(30.0, 300.0))
+        case = dict(name=f"rand{i}", nr=int(rng.integers(4, 400)), nth=int(rng.integers(4, 80)), rmin=rmin,
+                    rmax=rmax, a=float(rng.choice([0.0, rng.uniform(0.0, 0.99)])), m=int(rng.integers(-4, 7)),
+                    s=int(rng.integers(-2, 3)), robs=rmin + (rmax - rmin) * float(rng.uniform(0.05, 0.95)),
+                    n=int(rng.integers(5, 31)), rows=int(rng.choice([1, 2, 3, 5, 8, 13, 32, 64])),
+                    kb=int(rng.integers(1, 3)))
+        if rng.integers(0, 2):
+            case.update(r0=float(rng.uniform(6.0, 12.0)), amp=float(rng.uniform(0.5, 2.0)))
+        out.append(case)
+    return out
+
+
+@pytest.mark.parametrize("case", _random_cases(), ids=lambda c: c["name"])
+def test_parity_seeded_random_configurations(oracle_mod, case):
+    case = dict(case, dt=_dt(oracle_mod, case, 1000))
+    print(f"[gpu] random parity {case}", flush=True)
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=int(case["name"][4:]) + 100)
+    gp, gq, gw = run_gpu(case, phi, pi, case["n"], rows=case["rows"], kb=case["kb"])
+    op, oq, ow = run_oracle(oracle_mod, case, phi, pi, case["n"])
+    assert rel(gp, op) <= TOL64 and rel(gq, oq) <= TOL64, (rel(gp, op), rel(gq, oq))
+    assert rel(gw, ow) <= TOL64, rel(gw, ow)
