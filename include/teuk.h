@@ -26,8 +26,9 @@
  *     row) from teuk_create to teuk_destroy; a batch's tables and phase
  *     rows from teuk_batch_create to teuk_batch_destroy; and, for the
  *     duration of one call, the trial slots of teuk_adjoint_autotune and
- *     the two parameter-moved tables of teuk_param_gradient.  States,
- *     waveforms and workspaces are the caller's.
+ *     the two parameter-moved tables of teuk_param_gradient; and, once a
+ *     watchdog is set, 8 B of device and 8 B of pinned host memory per
+ *     context or batch.  States, waveforms and workspaces are the caller's.
  *   - Calls are asynchronous on the stream given at create unless noted.
  *   - Return value: TEUK_OK (0) or a negative TEUK_E* code.  No C++
  *     exception crosses the ABI.  A context is not thread safe; use one
