@@ -211,3 +211,34 @@ def test_batched_workload_sampled(oracle_mod):
         assert_same(batch_result(b, i, n + 1), ref, i)
     b.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("seed", [7, 11, 13])
+def test_batch_of_seeded_random_instances_is_bitwise(oracle_mod, seed):
+    """A batch of 5 seeded random instances (grid, spin, mode, source; see the
+    step's random parity cases) with a random tiling, steps per launch and
+    launch form equals 5 single-mode runs bit for bit."""
+    import torch
+    from paper_0909_4039_amd.batch import Batch, make_desc
+    from test_gpu_step import _random_cases
+    cases = _random_cases(k=5, seed=seed)
+    rng = np.random.default_rng(seed)
+    n = 12
+    descs, data = [], []
+    for i, c in enumerate(cases):
+        dt = oracle_mod.stable_dt(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], 1.0, c["m"], c["s"], 1000)
+        descs.append(make_desc(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], c["m"], dt, s=c["s"],
+                               r0=c.get("r0", 0.0), amp=c.get("amp", 0.0), rstar_obs=c["robs"]))
+        data.append(inputs.random_state(c["nr"], c["nth"], seed=seed * 10 + i))
+    rows, kb, persistent = int(rng.choice([0, 1, 3, 8, 32])), int(rng.integers(1, 3)), bool(rng.integers(0, 2))
+    print(f"[gpu] random batch seed={seed} rows={rows} kb={kb} persistent={persistent}", flush=True)
+    b = Batch(descs, n)
+    for i, (p, q) in enumerate(data):
+        b.set_state(i, p, q)
+    b.set_tiling(rows, kb, persistent)
+    b.step(n)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        got = batch_result(b, i, n + 1)
+        assert_same(got, single_mode(d, *data[i], n), f"instance {i}")
+    b.close()
