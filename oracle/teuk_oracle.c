@@ -67,7 +67,8 @@
  * NaN and only the exact domain of dependence survives.
  *
  * Parity status: the coefficient forms, the angular operator, the tortoise
- * map, the scheme's order of accuracy, the Schwarzschild l=2 ringdown, the
+ * map (and its printed values), the waveform extraction (exact for a field
+ * linear in r*, node values at nodes), the scheme's order of accuracy, the Schwarzschild l=2 ringdown, the
  * Kerr a = 0.5 l = m = 2 ringdown (which depends on every a-dependent
  * coefficient), the m -> -m mirror symmetry, the adjoint and the
  * moving-source gradients (central differences of the forward run) are
