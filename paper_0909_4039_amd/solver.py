@@ -90,7 +90,10 @@ class Solver:
         d = {"params": dict(self.params, prec=self.prec), "phi": self.phi.cpu(), "pi": self.pi.cpu(),
              "t": t, "step": step, "source": self.source, "trajectory": None}
         if self.trajectory is not None:
-            d["trajectory"] = torch.from_numpy(self.trajectory[2 * (step - self._traj_step0):].copy())
+            used = 2 * (step - self._traj_step0)   # entries consumed by the steps taken since the table was set
+            if used < 0:
+                raise RuntimeError("the orbit table starts after the current step")
+            d["trajectory"] = torch.from_numpy(self.trajectory[used:].copy())
         return d
 
     def load_state_dict(self, d):
@@ -153,7 +156,13 @@ class Solver:
         return t.value, n.value
 
     def set_time(self, t, step):
+        """Relabel the current step and time.  As in the library, the orbit
+        table stays attached to the same steps, so its first step moves by the
+        same amount."""
+        old = self.get_time()[1]
         check(_lib.lib().teuk_set_time(self._ctx, float(t), int(step)), self._ctx)
+        if self.trajectory is not None:
+            self._traj_step0 += int(step) - old
 
     def set_tiling(self, rows_per_wave, order=0):
         check(_lib.lib().teuk_set_tiling(self._ctx, int(rows_per_wave), int(order)), self._ctx)

@@ -57,6 +57,41 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral, prec):
     c.close()
 
 
+def test_checkpoint_after_relabelling_the_step_keeps_the_orbit(tmp_path):
+    # set_time relabels steps; the orbit table stays attached to the same
+    # steps, so a checkpoint taken after a relabel holds the unused entries.
+    import torch
+    from paper_0909_4039_amd.solver import suggest_dt
+    n = 24
+    dt = suggest_dt(NR, NTH, RMIN, RMAX, A, M, MM, S, 1000)
+    phi, pi = inputs.random_state(NR, NTH, 32)
+    a = make(dt)
+    a.set_source(9.0, 1.0)
+    a.set_trajectory(inputs.inspiral_trajectory(9.0, A, M, 0.05, dt, 3 * n))
+    a.set_state(phi, pi)
+    a.step(n)
+    t, _ = a.get_time()
+    a.set_time(t, 1000)                 # relabel the current step
+    a.step(n // 2)
+    torch.save(a.state_dict(), tmp_path / "ckpt.pt")
+    a.step(n)
+    torch.cuda.synchronize()
+    want = (a.phi.cpu().numpy(), a.pi.cpu().numpy(), a.get_time())
+    a.close()
+
+    b = make(dt)
+    d = torch.load(tmp_path / "ckpt.pt", weights_only=True)
+    assert d["step"] == 1000 + n // 2
+    assert d["trajectory"].shape[0] == 2 * (3 * n - n - n // 2) + 1
+    b.load_state_dict(d)
+    b.step(n)
+    torch.cuda.synchronize()
+    got = (b.phi.cpu().numpy(), b.pi.cpu().numpy(), b.get_time())
+    assert np.array_equal(want[0], got[0]) and np.array_equal(want[1], got[1])
+    assert got[2] == want[2]
+    b.close()
+
+
 def test_autotune_cache_reuses_a_choice(tmp_path):
     import torch
     from paper_0909_4039_amd import tune_cache
