@@ -99,6 +99,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libteuk.so not found at {LIB_PATH}; build it with "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # PyTorch ships its own HIP and HSA runtimes under the same sonames as
+        # the system's.  Importing it first makes the library bind to those, so
+        # the process holds one runtime; loaded the other way round, torch
+        # would bring up a second runtime beside the library's on the same GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
