@@ -178,6 +178,21 @@ int teuk_adjoint(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t 
                  void* workspace, int64_t workspace_bytes, void* dL_dphi0, void* dL_dpi0, double* dL_dr0,
                  double* dL_damp);
 
+/* The reverse sweep of teuk_adjoint without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  It calls no
+ * hipMalloc, hipFree or other allocating routine: its workspace is a
+ * file-scope device array of teuk_adjoint_noalloc_max_bytes() bytes
+ * (40 MiB, enough for a 4096 x 256 grid), which every GPU that runs this
+ * call holds until the process ends.  Arguments, results and errors are
+ * those of teuk_adjoint, plus TEUK_EINVAL when teuk_adjoint_workspace_bytes
+ * exceeds the array.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (other streams or threads) race and must be
+ * serialised by the caller.  Synchronous, as teuk_adjoint. */
+int64_t teuk_adjoint_noalloc_max_bytes(void);
+int teuk_adjoint_noalloc(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, int64_t n_steps, double t_start,
+                         void* dL_dphi0, void* dL_dpi0, double* dL_dr0, double* dL_damp);
+
 /* Reverse sweep for a moving source (FP64; the orbit table of
  * teuk_set_trajectory).  As teuk_adjoint, for a forward run of n_steps
  * steps from initial data u^0 that started at the table's first entry, so

@@ -55,6 +55,8 @@ _SIGS = {
     "teuk_adjoint_workspace_bytes": (_I64, [_P]),
     "teuk_adjoint": (ctypes.c_int, [_P, _D, _P, _I64, _D, _P, _I64, _P, _P, ctypes.POINTER(_D),
                                     ctypes.POINTER(_D)]),
+    "teuk_adjoint_noalloc_max_bytes": (_I64, []),
+    "teuk_adjoint_noalloc": (ctypes.c_int, [_P, _D, _P, _I64, _D, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "teuk_autotune": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "teuk_set_adjoint_tiling": (ctypes.c_int, [_P, _I32, _I32]),
     "teuk_param_gradient_workspace_bytes": (_I64, [_P, _I64, _I64]),

@@ -481,6 +481,12 @@ int adjoint_time_trial(teuk_ctx* c, int launches, double* slots, double* sec_per
 
 }  // namespace
 
+// Context accessors for the library's other translation units.
+namespace teuk {
+int ctx_device(const teuk_ctx* c) { return c->device; }
+int ctx_fail(teuk_ctx* c, int code, const char* msg) { return fail(c, code, "%s", msg); }
+}  // namespace teuk
+
 extern "C" {
 
 static int init_ctx(teuk_ctx* c, const teuk_grid* g, double a, double M, int32_t m, int32_t s, double dt,

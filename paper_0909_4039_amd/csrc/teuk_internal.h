@@ -195,6 +195,12 @@ struct BatchArgs {
     int32_t moving;           // 1: some instance has a moving source (the kernels built for it)
 };
 
+// Context accessors (defined with the context in teuk_api.cpp): the device
+// that was current at teuk_create, and recording a failure in the context
+// (sticky for TEUK_EDEVICE and TEUK_EUNSTABLE) while returning its code.
+int ctx_device(const teuk_ctx* c);
+int ctx_fail(teuk_ctx* c, int code, const char* msg);
+
 constexpr int WAVE = 64;
 constexpr int WG_WAVES = 4;
 
