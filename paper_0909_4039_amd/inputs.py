@@ -106,3 +106,10 @@ def inspiral_trajectory(r_start, a, M, q, dt, n_steps, substeps=8):
     out[:, 0] = r[::substeps]
     out[:, 1] = phi[::substeps]
     return out
+
+
+def projection_weights(shape, seed):
+    """Seeded complex weights with independent uniform real and imaginary parts
+    in [-1, 1), for random projections <w, u> = sum conj(w) u of a state."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, shape) + 1j * rng.uniform(-1.0, 1.0, shape)
