@@ -439,6 +439,16 @@ const char* teuk_strerror(int code);
 int teuk_suggest_dt(const teuk_grid* g, double a, double M, int32_t m, int32_t s,
                     int64_t n_steps, double* dt_out);
 
+/* Bandwidth probe (not part of the method): copy `bytes` (a multiple of 16)
+ * from src to dst, two non-overlapping 16-byte-aligned device buffers owned by
+ * the caller, with a plain streaming kernel on hip_stream (NULL: the null
+ * stream); asynchronous.  It measures what HBM delivers to a kernel that
+ * only reads and writes, the practical ceiling beside the step kernel's
+ * bandwidth, and it is the kernel of known traffic against which hardware
+ * byte counters are calibrated.  TEUK_EINVAL for bad sizes, alignment or
+ * overlap; TEUK_EDEVICE if the launch fails. */
+int teuk_stream_copy(const void* src, void* dst, int64_t bytes, void* hip_stream);
+
 /* Geometry probe (host only): r*(r) from Eq. (2) and its inverse as
  * delta = r - r+. */
 double teuk_rstar_of_r(double r, double a, double M);

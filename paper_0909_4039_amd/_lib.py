@@ -87,6 +87,7 @@ _SIGS = {
     "teuk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "teuk_suggest_dt": (ctypes.c_int, [ctypes.POINTER(TeukGrid), _D, _D, _I32, _I32, _I64,
                                        ctypes.POINTER(_D)]),
+    "teuk_stream_copy": (ctypes.c_int, [_P, _P, _I64, _P]),
     "teuk_rstar_of_r": (_D, [_D, _D, _D]),
     "teuk_delta_of_rstar": (_D, [_D, _D, _D]),
 }

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libteuk.so")
 SOURCES = ["teuk_api.cpp", "teuk_geom.cpp", "teuk_batch.cpp", "teuk_kernels.hip", "teuk_adjoint.hip",
-           "teuk_watch.hip", "teuk_noalloc.hip"]
+           "teuk_watch.hip", "teuk_probe.hip", "teuk_noalloc.hip"]
 ARCH = os.environ.get("TEUK_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
