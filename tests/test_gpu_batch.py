@@ -161,7 +161,8 @@ def test_batch_instance_against_oracle(oracle_mod):
                           amp=d.amp, rstar_obs=d.rstar_obs)
     op, oq, ow = o.run(*_data(i), n)
     gp, gq, gw = batch_result(b, i, n + 1)
-    rel = lambda x, y: np.linalg.norm(x - y) / np.linalg.norm(y)
+    rel = lambda x, y: max(np.linalg.norm(x - y) / np.linalg.norm(y),   # relative L2 and per element
+                           np.max(np.abs(x - y)) / np.max(np.abs(y)))
     assert rel(gp, op) <= 1e-12 and rel(gq, oq) <= 1e-12 and rel(gw, ow) <= 1e-12
     b.close()
 

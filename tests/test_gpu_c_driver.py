@@ -40,7 +40,7 @@ def test_c_example_matches_oracle(oracle_mod, tmp_path, nr, nth, a, m, s):
     o = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, dt, r0=r0, amp=amp, rstar_obs=robs)
     op, oq, ow = o.run(phi, pi, n)
     for name, g, ref in (("phi", gp, op), ("pi", gq, oq), ("wave", gw, ow)):
-        err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        err = max(np.linalg.norm(g - ref) / np.linalg.norm(ref), np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
         print(f"[gpu] C example {nr}x{nth} {name}: rel L2 {err:.2e}", flush=True)
         assert err <= 1e-12, (name, err)
 
@@ -54,7 +54,7 @@ def test_c_example_fp32(oracle_mod, tmp_path):
     gw = out[2 * nr * nth:].reshape(n + 1, nth)
     o = oracle_mod.Oracle(nr, nth, rmin, rmax, a, 1.0, m, s, dt, r0=r0, amp=amp, rstar_obs=robs)
     _, _, ow = o.run(phi, pi, n)
-    err = np.linalg.norm(gw - ow) / np.linalg.norm(ow)
+    err = max(np.linalg.norm(gw - ow) / np.linalg.norm(ow), np.max(np.abs(gw - ow)) / np.max(np.abs(ow)))
     print(f"[gpu] C example FP32 waveform: rel L2 {err:.2e}", flush=True)
     assert err <= 1e-5
 

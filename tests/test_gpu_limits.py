@@ -38,6 +38,7 @@ def _run(nr, nth, rmin, rmax, a, m, window, n, seed):
     assert ok.sum() > 0.3 * ok.size
     for g, r in ((gp, op), (gq, oq)):
         assert np.linalg.norm(g[ok] - r[ok]) <= 1e-12 * np.linalg.norm(r[ok])
+        assert np.max(np.abs(g[ok] - r[ok])) <= 1e-12 * np.max(np.abs(r[ok]))
     return rest
 
 
