@@ -54,6 +54,7 @@ extern "C" {
 
 #define TEUK_FP64 64
 #define TEUK_FP32 32
+#define TEUK_FP32S 48   /* FP32 storage (complex64 state and waveform), FP64 arithmetic and tables */
 
 typedef struct teuk_ctx teuk_ctx;
 
@@ -66,7 +67,10 @@ typedef struct {
 
 /* Create a solver for one (a, M, m, s) mode (Eq. 1, ansatz Eq. 4) with time
  * step dt on grid g.  prec is TEUK_FP64 or TEUK_FP32 (storage and
- * arithmetic).  hip_stream is a hipStream_t (NULL: the null stream).
+ * arithmetic), or TEUK_FP32S: FP32 storage of the state and the waveform
+ * (complex64, as TEUK_FP32) with each step computed in FP64 from FP64 tables
+ * (the FP32 bytes per point, FP64 rounding inside a step; no reverse sweep).
+ * hip_stream is a hipStream_t (NULL: the null stream).
  * Requires M > 0, 0 <= a < M, |s| <= 2, dt > 0.  Builds the radial tables
  * (r(r*) from Eq. 2 solved in ln(r - r+)) on the host in FP64 and uploads
  * them.  On success *out receives the context; on failure *out is NULL. */
@@ -135,8 +139,11 @@ int teuk_current(teuk_ctx* ctx);
 
 /* Tile shape of the step kernel (performance only; results are bitwise
  * identical for every choice): rows_per_wave theta rows per wavefront
- * (1..4096; 0 restores the default and ignores order) and the block order
- * (0: theta-chunk-major, 1: r*-strip-group-major). */
+ * (1..4096; 0 restores the default and ignores order) and the launch form:
+ * 0: one wavefront runs both fused steps of a tile, tiles theta-chunk-major;
+ * 1: the same, r*-strip-group-major; 2: two fused steps on a pair of
+ * wavefronts, one step each, handing rows over through LDS (single steps
+ * launch as for 0). */
 int teuk_set_tiling(teuk_ctx* ctx, int32_t rows_per_wave, int32_t order);
 int teuk_get_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* order);
 
@@ -259,9 +266,11 @@ int teuk_param_gradient(teuk_ctx* ctx, int32_t param, double h, double rstar_obs
 /* Autotuner (synchronous): times launches_per_trial launches (after one
  * warm-up launch) of every candidate tile shape -- theta rows per wavefront
  * in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256} clipped to
- * n_theta, times 1 or 2 steps per launch -- with HIP events on the
- * context's stream, keeps the fastest (chunk-major order) and reports it in
- * *rows_out and *kb_out (either may be NULL).  The results of teuk_step are
+ * n_theta, times three launch forms: 1 step per launch, 2 steps on one
+ * wavefront, 2 steps on a pair of wavefronts (teuk_set_tiling orders 0 and
+ * 2) -- with HIP events on the context's stream, keeps the fastest and
+ * reports its rows and steps per launch in *rows_out and *kb_out (either may
+ * be NULL; teuk_get_tiling reports the order).  The results of teuk_step are
  * bitwise identical for every candidate, so tuning changes speed only.
  * Needs a bound state; the trial launches read the current pair and write
  * the other one, so the state, time and waveform are unchanged.  The

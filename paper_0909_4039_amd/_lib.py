@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TEUK_LIB") or os.path.join(HERE, "libteuk.so")
 
 OK, EINVAL, ESTATE, EDEVICE, EUNSTABLE, ENOTSUP = 0, -1, -2, -3, -4, -5
-FP64, FP32 = 64, 32
+FP64, FP32, FP32S = 64, 32, 48   # FP32S: FP32 storage, FP64 arithmetic
 PARAM_A, PARAM_M, PARAM_R0, PARAM_AMP = 0, 1, 2, 3   # parameters of teuk_param_gradient
 
 

@@ -81,7 +81,9 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail((c), TEUK_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-size_t elem_size(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
+// Element size of the coefficient tables: FP64 for FP64 arithmetic (TEUK_FP64
+// and TEUK_FP32S), FP32 for TEUK_FP32.
+size_t elem_size(int prec) { return prec == TEUK_FP32 ? sizeof(float) : sizeof(double); }
 
 // Turn a watchdog finding that has reached the host into the sticky
 // TEUK_EUNSTABLE (no wait: a scan still in flight is seen by a later call).
@@ -95,7 +97,7 @@ int watch_poll(teuk_ctx* c) {
 int upload_tables(teuk_ctx* c) {
     const Geometry& g = c->geo;
     size_t nrad = g.rad_i.size(), nang = g.ang.size();
-    if (c->prec == 64) {
+    if (c->prec != TEUK_FP32) {
         HIP_TRY(c, hipMemcpyAsync(c->d_rad_i, g.rad_i.data(), nrad * 8, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->d_rad_h, g.rad_h.data(), nrad * 8, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->d_ang, g.ang.data(), nang * 8, hipMemcpyHostToDevice, c->stream));
@@ -123,7 +125,8 @@ StepArgs<R> step_args(const teuk_ctx* c) {
     a.nth = (int)g.nth;
     a.rows = c->rows;
     a.n_chunks = (int)((g.nth + c->rows - 1) / c->rows);
-    a.order = c->order;
+    a.order = c->order == 2 ? 0 : c->order;
+    a.split = c->order == 2 ? 1 : 0;   // two fused steps on a pair of wavefronts
     a.dt = (R)c->dt;
     a.hdt = (R)(0.5 * c->dt);
     a.inv_dr = (R)(1.0 / g.dr);
@@ -172,18 +175,21 @@ int launch_one(teuk_ctx* c, StepArgs<R>& a, int kb, int src, int64_t step, bool 
     a.pi = (const R*)c->buf[src][1];
     a.phi_out = (R*)c->buf[1 - src][0];
     a.pi_out = (R*)c->buf[1 - src][1];
-    if constexpr (std::is_same<R, double>::value) launch_step_fp64(a, c->stream);
-    else launch_step_fp32(a, c->stream);
+    if constexpr (std::is_same<R, double>::value) {
+        if (c->prec == TEUK_FP32S) launch_step_fp32s(a, c->stream);   // float state, FP64 arithmetic
+        else launch_step_fp64(a, c->stream);
+    } else {
+        launch_step_fp32(a, c->stream);
+    }
     HIP_TRY(c, hipGetLastError());
     return TEUK_OK;
 }
 
 // Watchdog scan of the current state (both fields), tagged with the step.
-template <typename R>
 int launch_watch(teuk_ctx* c) {
     const int64_t n = 2 * c->geo.nr * c->geo.nth;
     for (int f = 0; f < 2; ++f) {
-        if constexpr (std::is_same<R, double>::value)
+        if (c->prec == TEUK_FP64)
             launch_watch_fp64((const double*)c->buf[c->cur][f], n, c->watch_lim, c->step, c->d_watch, c->stream);
         else
             launch_watch_fp32((const float*)c->buf[c->cur][f], n, (float)c->watch_lim, c->step, c->d_watch,
@@ -207,7 +213,7 @@ int launch_steps(teuk_ctx* c, int64_t n) {
         c->step += kb;
         done += kb;
         if (c->watch_every > 0 && c->step % c->watch_every == 0) {
-            rc = launch_watch<R>(c);
+            rc = launch_watch(c);
             if (rc != TEUK_OK) return rc;
         }
     }
@@ -522,7 +528,7 @@ int teuk_create(const teuk_grid* g, double a, double M, int32_t m, int32_t s, do
     *out = nullptr;
     if (validate_phys(g, a, M, s) != TEUK_OK) return TEUK_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return TEUK_EINVAL;
-    if (prec != TEUK_FP64 && prec != TEUK_FP32) return TEUK_EINVAL;
+    if (prec != TEUK_FP64 && prec != TEUK_FP32 && prec != TEUK_FP32S) return TEUK_EINVAL;
     if (m < -1000 || m > 1000) return TEUK_EINVAL;
     teuk_ctx* c = new (std::nothrow) teuk_ctx();
     if (!c) return TEUK_EDEVICE;
@@ -657,7 +663,7 @@ static int teuk_step_impl(teuk_ctx* c, int64_t n) {
                         "it has %lld", (long long)s0, (long long)(s0 + n - 1), (long long)(2 * (s0 + n)),
                         (long long)c->traj_n);
     }
-    if (c->prec == 64) return launch_steps<double>(c, n);
+    if (c->prec != TEUK_FP32) return launch_steps<double>(c, n);
     return launch_steps<float>(c, n);
 }
 
@@ -711,7 +717,7 @@ int teuk_current(teuk_ctx* c) {
 
 int teuk_set_tiling(teuk_ctx* c, int32_t rows_per_wave, int32_t order) {
     if (!c) return TEUK_EINVAL;
-    if (order < 0 || order > 1) return fail(c, TEUK_EINVAL, "order must be 0 or 1");
+    if (order < 0 || order > 2) return fail(c, TEUK_EINVAL, "order must be 0, 1 or 2");
     if (rows_per_wave == 0) {
         c->rows = default_rows((int)c->geo.nth, c->kblock, c->prec);
         c->order = 0;
@@ -747,9 +753,12 @@ static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* 
     const int keep_rows = c->rows, keep_kb = c->kblock, keep_order = c->order;
     const bool keep_default = c->rows_default;
     double best = 0.0;
-    int best_rows = keep_rows, best_kb = keep_kb;
-    c->order = 0;
-    for (int kb = 1; kb <= KB_MAX; ++kb) {
+    int best_rows = keep_rows, best_kb = keep_kb, best_order = 0;
+    // launch forms: one step per launch; two fused steps on one wavefront
+    // (order 0) or on a pair of wavefronts (order 2)
+    static const int kForms[][2] = {{1, 0}, {2, 0}, {2, 2}};
+    for (const auto& form : kForms) {
+        const int kb = form[0];
         int prev = 0;
         for (int r : kRows) {
             const int rows = std::min(r, nth);
@@ -757,8 +766,9 @@ static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* 
             prev = rows;
             c->rows = rows;
             c->kblock = kb;
+            c->order = form[1];
             double sec = 0.0;
-            int rc = (c->prec == 64) ? time_trial<double>(c, launches_per_trial, &sec)
+            int rc = (c->prec != TEUK_FP32) ? time_trial<double>(c, launches_per_trial, &sec)
                                      : time_trial<float>(c, launches_per_trial, &sec);
             if (rc != TEUK_OK) {
                 c->rows = keep_rows;
@@ -771,11 +781,13 @@ static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* 
                 best = sec;
                 best_rows = rows;
                 best_kb = kb;
+                best_order = form[1];
             }
         }
     }
     c->rows = best_rows;
     c->kblock = best_kb;
+    c->order = best_order;
     c->rows_default = false;
     if (rows_out) *rows_out = best_rows;
     if (kb_out) *kb_out = best_kb;

@@ -49,6 +49,11 @@ __device__ __forceinline__ cx<R> stencil(R wp, cx<R> fp, R wm, cx<R> fm, R w0, c
     return rfma(wp, fp, rfma(wm, fm, w0 * f0));
 }
 
+// Conversion between storage and arithmetic precision (identity when equal;
+// double to float rounds to nearest).
+template <typename T, typename U>
+__device__ __forceinline__ cx<T> cvt(cx<U> v) { return {T(v.re), T(v.im)}; }
+
 template <typename R> struct vec2;
 template <> struct vec2<double> { using T = double2; };
 template <> struct vec2<float> { using T = float2; };

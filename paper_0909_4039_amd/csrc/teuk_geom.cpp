@@ -188,7 +188,7 @@ int default_rows(int nth, int kblock, int prec) {
     // Measured on 32768 x 1024: single steps prefer short chunks (16 rows:
     // many wavefronts, small tail); two fused steps need 4 halo rows per
     // side and prefer 64 (FP32) to 96 (FP64) rows.
-    int rows = (kblock >= 2) ? (prec == 64 ? 96 : 64) : 16;
+    int rows = (kblock >= 2) ? (prec == TEUK_FP32 ? 64 : 96) : 16;   // FP32 storage with FP64 arithmetic: as FP64
     return std::min(rows, std::max(nth, 1));
 }
 

@@ -98,6 +98,7 @@ struct StepArgs {
     int32_t n_tiles;   // n_strips * n_chunks
     int32_t order;     // block order: 0 chunk-major, 1 strip-group-major
     int32_t kb;        // steps in this launch (1 or 2)
+    int32_t split;     // kb = 2 on a pair of wavefronts, one step each (lw_step_split_kernel)
     R dt, hdt, inv_dr;
     R m2ma;            // -2 m a  (Sigma^2 Im c_r = m2ma w2)
     // per fused step k: e^{-i m Omega t^{n+k}} and e^{-i m Omega (t^{n+k} + dt/2)}
@@ -206,6 +207,9 @@ constexpr int WG_WAVES = 4;
 
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s);
 void launch_step_fp32(const StepArgs<float>& a, hipStream_t s);
+// FP32 storage with FP64 arithmetic: the state and waveform pointers of `a`
+// point to float.
+void launch_step_fp32s(const StepArgs<double>& a, hipStream_t s);
 void launch_extract_fp64(const double* phi, double* out, int nr, int nth, int iobs, double alpha,
                          hipStream_t s);
 void launch_extract_fp32(const float* phi, float* out, int nr, int nth, int iobs, float alpha,

@@ -14,10 +14,12 @@
 // valid column per side, so lanes KB..63-KB produce outputs and
 // neighbouring strips overlap by 2KB columns.  Along theta the three-point
 // angular stencil of each stage is accumulated as a partial sum (the part
-// that needs rows j-1 and j as soon as row j is known, the row j+1 term one
-// row later), so u^n is read from HBM once per row (plus 2KB halo rows per
-// side of a chunk) and u^{n+KB} written once: 64 B per grid point per
-// launch in FP64, 32 B in FP32.  Intermediate values never leave registers.
+// that needs rows j-1 and j, times the stage's weight D, is added to the
+// pending Pi as soon as row j is known; the row j+1 term one row later), so
+// u^n is read from HBM once per row (plus 2KB halo rows per side of a chunk)
+// and u^{n+KB} written once: 64 B per grid point per launch in FP64, 32 B in
+// FP32 (also when FP32 storage is combined with FP64 arithmetic).
+// Intermediate values never leave registers.
 //
 // Coefficients.  All coefficients of Eqs. (5)-(12) are separable into
 // radial numerators (per-wave LDS for the lane's column) and angular
@@ -63,7 +65,7 @@ struct Stage {
     R dw;
 };
 
-template <typename R>
+template <bool SRC, typename R>
 __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, R gr, const Ang<R>& g, R m2ma_idr, R idr, R tau,
                                           cx<R> ph, cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df, cx<R> dg) {
     R S2 = fma(q.w2, q.w2, -g.a2s2 * q.del);   // Sigma^2
@@ -75,32 +77,38 @@ __device__ __forceinline__ Stage<R> stage(const Rad<R>& q, R gr, const Ang<R>& g
     cx<R> CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
     cx<R> V = {q.vr, q.vi};
     cx<R> acc = cfma(CR, df, cfma(V, f, cmul(CT, X)));
-    cx<R> T = (g.agth * gr) * ph;   // source: amp x theta Gaussian x radial factor x phase
     Stage<R> o;
     o.phi = {fma(tau, X.re, f0.re), fma(tau, X.im, f0.im)};
-    cx<R> rhs = {fma(bi, dg.re, fma(-y2, acc.re, T.re)), fma(bi, dg.im, fma(-y2, acc.im, T.im))};
+    cx<R> rhs;
+    if constexpr (SRC) {
+        cx<R> T = (g.agth * gr) * ph;   // source: amp x theta Gaussian x radial factor x phase
+        rhs = {fma(bi, dg.re, fma(-y2, acc.re, T.re)), fma(bi, dg.im, fma(-y2, acc.im, T.im))};
+    } else {
+        // a tile where T = 0 at every point: the same values up to the sign
+        // of a zero
+        rhs = {fma(bi, dg.re, -y2 * acc.re), fma(bi, dg.im, -y2 * acc.im)};
+    }
     o.pi_part = {fma(tau, rhs.re, g0.re), fma(tau, rhs.im, g0.im)};
     o.dw = tau * q.del * y2;
     return o;
 }
 
 // State of one Lax-Wendroff step marching upwards through theta (one
-// pipeline stage).  The three-point angular stencil of each stage,
-// wp f(j+1) + (wm f(j-1) + w0 f(j)), is formed in two parts: the bracket as
-// soon as row j is known, the wp term one row later.  Only one previous row
-// and one partial sum per stage are carried.
+// pipeline stage).  The angular term D (wp f(j+1) + wm f(j-1) + w0 f(j)) of
+// each stage is formed in two parts: D times the bracket wm f(j-1) + w0 f(j)
+// goes into the pending Pi as soon as row j is known, and the carried weight
+// D wp multiplies f(j+1) one row later.  Only one previous row and the
+// pending values of each stage are carried.
 template <typename R>
 struct Pipe {
     cx<R> pb_prev;  // Phi sum (twice the mean) at half point c+1/2, time n, row L-1
-    cx<R> pb_acc;   // bracket of the predictor's stencil for half row L-1
     cx<R> ph_prev;  // Phi sum of doubled half values (4x the mean) at c, time n+1/2, row L-2
-    cx<R> ph_acc;   // bracket of the corrector's stencil for row L-2
     // Each Lax-Wendroff stage is split into its angular part, which needs the
     // next row, and the rest.  Pending (non-angular) parts:
-    cx<R> hP, hQp;  // predictor of half row L-1, doubled: final Phi, partial Pi
-    R hD;           // (dt/2) Delta/Sigma^2 at that half row
-    cx<R> nQp;      // corrector of row L-2: partial Pi
-    R nD;           // dt Delta/Sigma^2 at that row
+    cx<R> hP, hQp;  // predictor of half row L-1, doubled: final Phi, Pi but for the wp term
+    R hD;           // (dt/2) (Delta/Sigma^2) wp at that half row: the weight of row L
+    cx<R> nQp;      // corrector of row L-2: Pi but for the wp term
+    R nD;           // dt (Delta/Sigma^2) wp at that row: the weight of row L-1's half values
     cx<R> up, uq;   // input row L-1 (the u^n term of the corrector)
     int olo, ohi;   // rows [olo, ohi) whose outputs this stage produces
     int ihi;        // input rows end at ihi (they start at olo - 2, clipped at 0)
@@ -110,7 +118,7 @@ struct Pipe {
 template <typename R>
 __device__ __forceinline__ void pipe_init(Pipe<R>& st, int olo, int ohi, int nth) {
     const cx<R> zero = {R(0), R(0)};
-    st.pb_prev = zero; st.pb_acc = zero; st.ph_prev = zero; st.ph_acc = zero;
+    st.pb_prev = zero; st.ph_prev = zero;
     st.hP = zero; st.hQp = zero; st.hD = R(0); st.nQp = zero; st.nD = R(0);
     st.up = zero; st.uq = zero;
     st.olo = olo; st.ohi = ohi;
@@ -132,10 +140,17 @@ struct Consts {
 // One iteration of a stage at its row index L with input row L = (p, q).
 // Returns the stage's finished outputs: Phi at row L-1 (okP) and Pi at row
 // L-2 (okQ).  The parts of the iteration sit behind wave-uniform branches,
-// which also keep the scheduler from stretching live ranges.
-template <typename R>
+// which also keep the scheduler from stretching live ranges.  EDGE: the
+// tile holds an r* boundary column or a nonzero source value; other tiles
+// skip the boundary factor (1 at every column they hold) and the source term
+// (0 at every point they hold).
+//
+// NB: the input row's values at column c+1 arrive in (p1n, q1n), read from
+// LDS by the caller, instead of by a lane shift.
+template <bool EDGE, bool NB = false, typename R, typename S>
 __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int ks, int L, cx<R> p, cx<R> q,
-                                          cx<R> ph0, cx<R> ph1, R* wave, int64_t wrow, int wl, int rlo,
+                                          cx<R> p1n, cx<R> q1n,
+                                          cx<R> ph0, cx<R> ph1, S* wave, int64_t wrow, int wl, int rlo,
                                           int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
     const cx<R> zero = {R(0), R(0)};
     const int P = L - 1, Q = L - 2;
@@ -146,22 +161,24 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
     // (rows past the grid keep a zero sum: they meet only zero weights)
     cx<R> pbL = zero, Qb, dP, dQ;   // Qb, dP, dQ are read only by A2, which implies A1 ran
     if (L < st.ihi) {
-        cx<R> p1 = shfl_dn1(p), q1 = shfl_dn1(q);
+        cx<R> p1 = p1n, q1 = q1n;
+        if constexpr (!NB) {
+            p1 = shfl_dn1(p);
+            q1 = shfl_dn1(q);
+        }
         pbL = p + p1;            // twice the mean (see stage())
         Qb = q + q1;
         dP = p1 - p;             // unscaled: 1/dr* is folded into the stage
         dQ = q1 - q;
         if (wrow >= 0 && L >= rlo && L < rhi) {
-            if (K.lane == wl) stc(wave, wrow * K.nth + L, rfma(alpha, p1, (R(1) - alpha) * p));
+            if (K.lane == wl) stc(wave, wrow * K.nth + L, cvt<S>(rfma(alpha, p1, (R(1) - alpha) * p)));
         }
     }
     // ---- B1: finish the predictor (Eq. 13) of half row P and form the
     //      corrector's means and differences at c (time n+1/2)
     cx<R> phL = zero, Qh, dhP, dhQ;  // Qh, dhP, dhQ are read only by B2, whose rows are a subset
     if (P >= st.plo && P <= st.phi) {
-        const R wp = ang_at(K.ang, P, A_P);
-        cx<R> Lf = rfma(wp, pbL, st.pb_acc);
-        cx<R> hQ = rfma(st.hD, Lf, st.hQp);
+        cx<R> hQ = rfma(st.hD, pbL, st.hQp);
         cx<R> hPm = shfl_up1(st.hP), hQm = shfl_up1(hQ);
         phL = st.hP + hPm;       // four times the mean: the half-step values are doubled
         Qh = hQ + hQm;
@@ -173,20 +190,18 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
     if (L >= st.plo && L <= st.phi) {
         const Ang<R> g = load_ang(K.ang, L);
         const Rad<R> qh = lds_rad_fwd<R>(K.srad[0], K.lane);   // half point c+1/2
-        const R gr = lds_lane(K.ssrc[ks][0], K.lane);
-        Stage<R> o = stage(qh, gr, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
+        const R gr = EDGE ? lds_lane(K.ssrc[ks][0], K.lane) : R(0);
+        Stage<R> o = stage<EDGE>(qh, gr, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
         st.hP = o.phi;
-        st.hQp = o.pi_part;
-        st.hD = o.dw;
-        st.pb_acc = rfma(g.wm, st.pb_prev, g.w0 * pbL);
+        st.hQp = rfma(o.dw, rfma(g.wm, st.pb_prev, g.w0 * pbL), o.pi_part);
+        st.hD = o.dw * g.wp;
     }
     st.pb_prev = pbL;
     // ---- C: finish the corrector (Eq. 14) of row Q: its Pi
     okQ = (Q >= st.olo && Q < st.ohi);
     if (okQ) {
-        const R wp = ang_at(K.ang, Q, A_P);
-        cx<R> Lf = rfma(wp, phL, st.ph_acc);
-        outQ = K.keep * rfma(st.nD, Lf, st.nQp);
+        outQ = rfma(st.nD, phL, st.nQp);
+        if constexpr (EDGE) outQ = K.keep * outQ;
     }
     // ---- B2: non-angular part of the corrector of row P (its Phi is final)
     //      and the bracket of its stencil
@@ -194,31 +209,97 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
     if (okP) {
         const Ang<R> g = load_ang(K.ang, P);
         const Rad<R> qi = lds_rad_fwd<R>(K.srad[1], K.lane);   // integer point c
-        const R gr = lds_lane(K.ssrc[ks][1], K.lane);
-        Stage<R> o = stage(qi, gr, g, K.m2ma_idr, K.idr, K.qdt, ph1, up, uq, phL, Qh, dhP, dhQ);
-        st.nQp = o.pi_part;
-        st.nD = o.dw;
-        outP = K.keep * o.phi;
-        st.ph_acc = rfma(g.wm, st.ph_prev, g.w0 * phL);
+        const R gr = EDGE ? lds_lane(K.ssrc[ks][1], K.lane) : R(0);
+        Stage<R> o = stage<EDGE>(qi, gr, g, K.m2ma_idr, K.idr, K.qdt, ph1, up, uq, phL, Qh, dhP, dhQ);
+        st.nQp = rfma(o.dw, rfma(g.wm, st.ph_prev, g.w0 * phL), o.pi_part);
+        st.nD = o.dw * g.wp;
+        outP = EDGE ? K.keep * o.phi : o.phi;
     }
     st.ph_prev = phL;
 }
 
+// The row march of one tile (see step_tile): stage k advances u^{n+k} to
+// u^{n+k+1} and consumes row X of stage k-1's output once both its Phi
+// (finished one iteration earlier) and its Pi are final, two rows behind.
+// S is the storage type of the state and the waveform, R the arithmetic's.
+template <typename S, typename R, int KB, bool EDGE, typename P>
+__device__ __forceinline__ void march(const S* __restrict__ phi, const S* __restrict__ pi,
+                                      S* __restrict__ phi_out, S* __restrict__ pi_out, S* __restrict__ wave,
+                                      const P& A, const Consts<R>& K, int j0, int jend, unsigned boff,
+                                      unsigned soff, bool out_lane, bool rec, int wl) {
+    const int nr = A.nr(), nth = A.nth();
+    const cx<R> zero = {R(0), R(0)};
+    // stage k produces rows [j0 - 2(KB-1-k), jend + 2(KB-1-k)), clipped
+    Pipe<R> st[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        pipe_init(st[k], max(j0 - 2 * (KB - 1 - k), 0), min(jend + 2 * (KB - 1 - k), nth), nth);
+    const int Ls = max(st[0].olo - 2, 0);          // first input row of stage 0
+    const int Le = jend - 1 + 2 * KB;             // last iteration: the last stage's C at row jend-1
+    cx<R> held[KB];                               // Phi of stage k's output row L-1, kept one iteration
+#pragma unroll
+    for (int k = 0; k < KB; ++k) held[k] = zero;
+
+    // input rows of stage 0 in flight two ahead: rows Ls and Ls+1 now,
+    // iteration L requests row L+2 into the buffer row L came in
+    const cx<S> zs = {S(0), S(0)};
+    cx<S> pa_p = ld_row_once(phi, (int64_t)Ls * nr, boff), pa_q = ld_row_once(pi, (int64_t)Ls * nr, boff);
+    cx<S> pb_p = zs, pb_q = zs;
+    if (Ls + 1 < st[0].ihi && Ls + 1 <= Le) {
+        pb_p = ld_row_once(phi, (int64_t)(Ls + 1) * nr, boff);
+        pb_q = ld_row_once(pi, (int64_t)(Ls + 1) * nr, boff);
+    }
+
+    auto iter = [&](int L, cx<S>& pf_p, cx<S>& pf_q) {
+        if (L > Le) return;
+        cx<R> p = cvt<R>(pf_p), q = cvt<R>(pf_q);
+        if (L + 2 < st[0].ihi && L + 2 <= Le) {
+            const int64_t row = (int64_t)(L + 2) * nr;
+            pf_p = ld_row_once(phi, row, boff);
+            pf_q = ld_row_once(pi, row, boff);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int Lk = L - 2 * k;   // stage k works two rows behind stage k-1
+            cx<R> oP, oQ;
+            bool okP, okQ;
+            const cx<R> ph0 = A.ph(2 * k), ph1 = A.ph(2 * k + 1);
+            pipe_iter<EDGE>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend,
+                            A.alpha(), oP, okP, oQ, okQ);
+            if (k == KB - 1) {
+                if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, cvt<S>(oQ));
+                if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, cvt<S>(oP));
+            } else {
+                // next stage's input row Lk-2: Phi finished one iteration ago,
+                // Pi finished now
+                p = held[k];
+                q = oQ;
+                if (okP) held[k] = oP;
+            }
+        }
+    };
+    // unrolled twice so that the carried values alternate between register sets
+    for (int L = Ls; L <= Le; L += 2) {
+        iter(L, pa_p, pa_q);
+        iter(L + 1, pb_p, pb_q);
+    }
+}
+
 // KB Lax-Wendroff steps over one tile (one wavefront's strip of r* columns
 // and its chunk of theta rows), the work unit of both the single-mode and
-// the batched kernel.  Stage k advances u^{n+k} to u^{n+k+1}; the
-// intermediate states never leave registers: stage k+1 consumes row X of
-// stage k's output once both its Phi (finished one iteration earlier) and
-// its Pi are final, two rows behind.  Each stage's arithmetic per point is
-// the same code as for KB = 1, so results are bitwise identical to KB
-// single steps whatever the tiling or batching.  A strip loses one valid
-// column per side and a chunk needs two more halo rows per side for each
-// extra stage.  `srad` is this wavefront's own LDS slice (no barrier).
-template <typename R, int KB, typename P>
-__device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __restrict__ pi,
-                                          R* __restrict__ phi_out, R* __restrict__ pi_out,
+// the batched kernel.  The intermediate states never leave registers.  Each
+// stage's arithmetic per point is the same code as for KB = 1, so results
+// are bitwise identical to KB single steps whatever the tiling or batching.
+// A strip loses one valid column per side and a chunk needs two more halo
+// rows per side for each extra stage.  `lds` is this wavefront's own slice
+// (no barrier).  S: storage type of the state; R: arithmetic type (FP32
+// storage with FP64 arithmetic converts on load and store).
+template <typename S, typename R, int KB, typename P>
+__device__ __forceinline__ void step_tile(const S* __restrict__ phi, const S* __restrict__ pi,
+                                          S* __restrict__ phi_out, S* __restrict__ pi_out,
                                           const R* __restrict__ rad_i, const R* __restrict__ rad_h,
-                                          const R* __restrict__ ang, R* __restrict__ wave, const P& A,
+                                          const R* __restrict__ ang, S* __restrict__ wave, const P& A,
                                           int strip, int chunk, FwdLds<R, KB>* lds) {
     constexpr int SO = WAVE - 2 * KB;   // valid output columns per strip
     const int lane = threadIdx.x & (WAVE - 1);
@@ -240,6 +321,7 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     // source radial factor of each fused step at its predictor (half point,
     // t^{n+k}) and corrector (integer point, t^{n+k} + dt/2): the table's
     // for a fixed orbit, exp(-(r* - r*0(t))^2 / (2 sr^2)) for a moving one
+    bool src_here = false;   // a column of this lane meets the source
 #pragma unroll
     for (int k = 0; k < KB; ++k)
         for (int loc = 0; loc < 2; ++loc) {
@@ -251,12 +333,13 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
                 v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * A.stride() + cu];
             }
             lds->src[k][loc][lane] = v * (loc == 0 ? R(2) : R(4));   // 2T predictor, 4T corrector
+            src_here = src_here || (v != R(0) && c >= 0 && c < nr);
         }
     const int j0 = chunk * A.rows();
     const int jend = min(j0 + A.rows(), nth);
     const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
-    const unsigned boff = cu * (unsigned)(2 * sizeof(R));          // byte offset of this lane's column
-    const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(R));
+    const unsigned boff = cu * (unsigned)(2 * sizeof(S));          // byte offset of this lane's column
+    const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(S));
     Consts<R> K;
     K.ang = ang;
     K.srad = srad;
@@ -271,57 +354,13 @@ __device__ __forceinline__ void step_tile(const R* __restrict__ phi, const R* __
     // recorder: the strip holding columns iobs and iobs+1 among its lanes
     const bool rec = (A.iobs() / SO == strip);
     const int wl = A.iobs() - strip * SO + KB;
-    const cx<R> zero = {R(0), R(0)};
-
-    // stage k produces rows [j0 - 2(KB-1-k), jend + 2(KB-1-k)), clipped
-    Pipe<R> st[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k)
-        pipe_init(st[k], max(j0 - 2 * (KB - 1 - k), 0), min(jend + 2 * (KB - 1 - k), nth), nth);
-    const int Ls = max(st[0].olo - 2, 0);          // first input row of stage 0
-    const int Le = jend - 1 + 2 * KB;             // last iteration: the last stage's C at row jend-1
-    cx<R> held[KB];                               // Phi of stage k's output row L-1, kept one iteration
-#pragma unroll
-    for (int k = 0; k < KB; ++k) held[k] = zero;
-
-    // prefetched input row of stage 0 (row Ls is always inside the grid)
-    cx<R> pf_p = ld_row_once(phi, (int64_t)Ls * nr, boff), pf_q = ld_row_once(pi, (int64_t)Ls * nr, boff);
-
-    auto iter = [&](int L) {
-        if (L > Le) return;
-        // Row L was requested by the previous iteration; request row L+1 now.
-        cx<R> p = pf_p, q = pf_q;
-        if (L + 1 < st[0].ihi && L + 1 <= Le) {
-            const int64_t row = (int64_t)(L + 1) * nr;
-            pf_p = ld_row_once(phi, row, boff);
-            pf_q = ld_row_once(pi, row, boff);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int Lk = L - 2 * k;   // stage k works two rows behind stage k-1
-            cx<R> oP, oQ;
-            bool okP, okQ;
-            const cx<R> ph0 = A.ph(2 * k), ph1 = A.ph(2 * k + 1);
-            pipe_iter(st[k], K, k, Lk, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend, A.alpha(),
-                      oP, okP, oQ, okQ);
-            if (k == KB - 1) {
-                if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, oQ);
-                if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, oP);
-            } else {
-                // next stage's input row Lk-2: Phi finished one iteration ago,
-                // Pi finished now
-                p = held[k];
-                q = oQ;
-                if (okP) held[k] = oP;
-            }
-        }
-    };
-    // unrolled twice so that the carried values alternate between register sets
-    for (int L = Ls; L <= Le; L += 2) {
-        iter(L);
-        iter(L + 1);
-    }
+    // Tiles with an r* boundary column or a nonzero source value take the
+    // general code; all others skip the boundary factor and the source term.
+    const bool edge = __ballot(K.keep == R(0) || src_here) != 0;
+    if (edge)
+        march<S, R, KB, true>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
+    else
+        march<S, R, KB, false>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
 }
 
 // Per-tile constants of the single-mode kernel: its kernel argument (the
@@ -349,13 +388,14 @@ struct ArgParams {
 };
 
 // Single-mode launch: one tile per wavefront, WG_WAVES adjacent strips of
-// the same theta chunk per workgroup.
-template <typename R, int KB>
-__global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi, const R* __restrict__ pi,
-                                                    R* __restrict__ phi_out, R* __restrict__ pi_out,
-                                                    const R* __restrict__ rad_i, const R* __restrict__ rad_h,
-                                                    const R* __restrict__ ang, R* __restrict__ wave,
-                                                    StepArgs<R> A) {
+// the same theta chunk per workgroup.  S: storage type of the state and the
+// waveform; R: arithmetic type.  The FP64 body fits 3 waves per SIMD (168
+// VGPRs); the hint keeps the allocator there.
+template <typename S, typename R, int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void lw_step_kernel(
+    const S* __restrict__ phi, const S* __restrict__ pi, S* __restrict__ phi_out, S* __restrict__ pi_out,
+    const R* __restrict__ rad_i, const R* __restrict__ rad_h, const R* __restrict__ ang, S* __restrict__ wave,
+    StepArgs<R> A) {
     // wave-uniform quantities: keep them in scalar registers
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     // Every row access of a workgroup is one contiguous 4 KiB (FP64) span.
@@ -377,21 +417,204 @@ __global__ __launch_bounds__(256) void lw_step_kernel(const R* __restrict__ phi,
     if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
     __shared__ FwdLds<R, KB> lds_all[WG_WAVES];   // one slice per wavefront
     const ArgParams<R> P{A};
-    step_tile<R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, &lds_all[wid]);
+    step_tile<S, R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, &lds_all[wid]);
 }
 
+
+// Two fused steps on a pair of wavefronts.  The single-wave tile above keeps
+// both steps' pipelines in one wavefront's registers (3 waves per SIMD in
+// FP64).  Here a workgroup of two wavefronts takes one strip and one theta
+// chunk: wave 0 runs the first step's pipeline over the rows of u^n read
+// from HBM, wave 1 the second step's over the rows of u^{n+1} that wave 0
+// hands over through an LDS ring, and writes u^{n+2}.  Each wave carries one
+// pipeline, and the two share the strip's radial tables.  The arithmetic per
+// point is step_tile's (the same stage code), so results are bitwise
+// identical to it and to single steps.
+//
+// Wave 0 finishes Phi of row L-1 and Pi of row L-2 at its iteration L and
+// puts them in ring slot (row & 3).  Wave 1 takes row L-3 at iteration L, so
+// a row is complete one iteration before it is read; both waves meet at one
+// barrier per iteration, and a slot is rewritten only after two more
+// barriers.  Wave 1 reads column c+1 of its input row from the ring instead
+// of shifting lanes.
+constexpr int RING = 4;
+
 template <typename R>
+struct SplitLds {
+    R rad[2][N_RAD_FWD][WAVE];
+    R src[2][2][WAVE];
+    cx<R> ring[RING][2][WAVE + 1];   // [slot][Phi, Pi][lane]; lane 64 feeds only lane 63
+};
+
+// LDS barrier of the pair: LDS and scalar operations complete, then s_barrier.
+// Vector memory is not waited for (the pair shares no global data).
+__device__ __forceinline__ void pair_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <typename S, typename R, bool EDGE, typename P>
+__device__ __forceinline__ void split_march(const S* __restrict__ phi, const S* __restrict__ pi,
+                                            S* __restrict__ phi_out, S* __restrict__ pi_out, S* __restrict__ wave,
+                                            const P& A, const Consts<R>& K, SplitLds<R>* lds, int wid, int j0,
+                                            int jend, unsigned boff, unsigned soff, bool out_lane, bool rec,
+                                            int wl) {
+    const int nr = A.nr(), nth = A.nth();
+    const int Ls = max(j0 - 4, 0);     // first input row of the first step
+    const int Le = jend + 3;           // the second step's C at row jend-1 comes at L = Le + 1
+    const int lane = K.lane;
+    if (wid == 0) {
+        Pipe<R> st;
+        pipe_init(st, max(j0 - 2, 0), min(jend + 2, nth), nth);
+        const cx<R> ph0 = A.ph(0), ph1 = A.ph(1);
+        const int64_t wrow = rec ? A.wave_row(0) : -1;
+        const cx<S> zs = {S(0), S(0)};
+        cx<S> pa_p = ld_row_once(phi, (int64_t)Ls * nr, boff), pa_q = ld_row_once(pi, (int64_t)Ls * nr, boff);
+        cx<S> pb_p = zs, pb_q = zs;
+        if (Ls + 1 < st.ihi) {
+            pb_p = ld_row_once(phi, (int64_t)(Ls + 1) * nr, boff);
+            pb_q = ld_row_once(pi, (int64_t)(Ls + 1) * nr, boff);
+        }
+        auto it = [&](int L, cx<S>& pf_p, cx<S>& pf_q) {
+            cx<R> p = cvt<R>(pf_p), q = cvt<R>(pf_q);
+            if (L + 2 < st.ihi) {
+                const int64_t row = (int64_t)(L + 2) * nr;
+                pf_p = ld_row_once(phi, row, boff);
+                pf_q = ld_row_once(pi, row, boff);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            cx<R> oP, oQ;
+            bool okP, okQ;
+            pipe_iter<EDGE>(st, K, 0, L, p, q, p, q, ph0, ph1, wave, wrow, wl, j0, jend, A.alpha(), oP, okP, oQ,
+                            okQ);
+            if (okP) lds->ring[(L - 1) & (RING - 1)][0][lane] = oP;
+            if (okQ) lds->ring[(L - 2) & (RING - 1)][1][lane] = oQ;
+            pair_barrier();
+        };
+        int L = Ls;
+        for (; L + 1 <= Le + 1; L += 2) {
+            it(L, pa_p, pa_q);
+            it(L + 1, pb_p, pb_q);
+        }
+        if (L <= Le + 1) it(L, pa_p, pa_q);
+    } else {
+        Pipe<R> st;
+        pipe_init(st, j0, jend, nth);
+        const cx<R> ph0 = A.ph(2), ph1 = A.ph(3);
+        const int64_t wrow = rec ? A.wave_row(1) : -1;
+        for (int L = Ls; L <= Le + 1; ++L) {
+            const int X = L - 3;     // this step's input row
+            const int slot = X & (RING - 1);
+            const cx<R> p = lds->ring[slot][0][lane], q = lds->ring[slot][1][lane];
+            const cx<R> p1 = lds->ring[slot][0][lane + 1], q1 = lds->ring[slot][1][lane + 1];
+            cx<R> oP, oQ;
+            bool okP, okQ;
+            pipe_iter<EDGE, true>(st, K, 1, X, p, q, p1, q1, ph0, ph1, wave, wrow, wl, j0, jend, A.alpha(), oP, okP,
+                                  oQ, okQ);
+            if (okQ && out_lane) st_row(pi_out, (int64_t)(X - 2) * nr, soff, cvt<S>(oQ));
+            if (okP && out_lane) st_row(phi_out, (int64_t)(X - 1) * nr, soff, cvt<S>(oP));
+            pair_barrier();
+        }
+    }
+}
+
+// Grid: one workgroup (two wavefronts) per tile, tiles chunk-major in
+// XCD-aware order.  4 pairs per SIMD need at most 128 VGPRs.
+template <typename S, typename R>
+__global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(4))) void lw_step_split_kernel(
+    const S* __restrict__ phi, const S* __restrict__ pi, S* __restrict__ phi_out, S* __restrict__ pi_out,
+    const R* __restrict__ rad_i, const R* __restrict__ rad_h, const R* __restrict__ ang, S* __restrict__ wave,
+    StepArgs<R> A) {
+    constexpr int KB = 2, SO = WAVE - 2 * KB;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = tile / A.n_strips, strip = tile - chunk * A.n_strips;
+    __shared__ SplitLds<R> lds;
+    const ArgParams<R> P{A};
+    const int nr = P.nr(), nth = P.nth();
+    const int c = strip * SO - KB + lane;
+    const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
+    const R idr = R(2) * P.inv_dr();
+    // the strip's radial numerators: each wave writes half of the fields
+    for (int k = wid; k < 2 * N_RAD_FWD; k += 2) {
+        const int loc = k / N_RAD_FWD, f = k % N_RAD_FWD;
+        const R v = (loc == 0 ? rad_h : rad_i)[(int64_t)f * P.stride() + cu];
+        lds.rad[loc][f][lane] = (f == R_CRR || f == R_WBN) ? v * idr : v;
+    }
+    // source radial factors of both steps (each wave its own step's), and
+    // whether any column of the strip meets the source (both waves alike)
+    bool src_here = false;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        for (int loc = 0; loc < 2; ++loc) {
+            R v;
+            if (P.moving()) {
+                const R x = fma((R)c + (loc == 0 ? R(0.5) : R(0)), P.dr(), P.rmin()) - P.rs0(2 * k + loc);
+                v = exp((-x * x) / P.two_sr2());
+            } else {
+                v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * P.stride() + cu];
+            }
+            if (k == wid) lds.src[k][loc][lane] = v * (loc == 0 ? R(2) : R(4));
+            src_here = src_here || (v != R(0) && c >= 0 && c < nr);
+        }
+    // The ring starts at zero: wave 1's pipeline reads rows before the first
+    // one wave 0 hands over (their values meet only zero weights, as the
+    // zero-initialised carried rows of the single-wave tile do).
+    {
+        const cx<R> zero = {R(0), R(0)};
+        for (int k = 0; k < RING; ++k) {
+            lds.ring[k][wid][lane] = zero;
+            if (lane == 0) lds.ring[k][wid][WAVE] = zero;
+        }
+    }
+    pair_barrier();
+    const int j0 = chunk * P.rows();
+    const int jend = min(j0 + P.rows(), nth);
+    const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
+    const unsigned boff = cu * (unsigned)(2 * sizeof(S));
+    const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(S));
+    Consts<R> K;
+    K.ang = ang;
+    K.srad = lds.rad;
+    K.ssrc = lds.src;
+    K.lane = lane;
+    K.nth = nth;
+    K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);
+    K.idr = idr;
+    K.qdt = R(0.25) * P.dt();
+    K.hdt = P.hdt();
+    K.m2ma_idr = P.m2ma() * idr;
+    const bool rec = (P.iobs() / SO == strip);
+    const int wl = P.iobs() - strip * SO + KB;
+    const bool edge = __ballot(K.keep == R(0) || src_here) != 0;
+    if (edge)
+        split_march<S, R, true>(phi, pi, phi_out, pi_out, wave, P, K, &lds, wid, j0, jend, boff, soff, out_lane, rec,
+                                wl);
+    else
+        split_march<S, R, false>(phi, pi, phi_out, pi_out, wave, P, K, &lds, wid, j0, jend, boff, soff, out_lane,
+                                 rec, wl);
+}
+
+// S: storage type; the state and waveform pointers of `a` point to S.
+template <typename S, typename R>
 static void launch_step(const StepArgs<R>& a, hipStream_t s) {
     int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
-    if (a.kb == 2)
-        hipLaunchKernelGGL((lw_step_kernel<R, 2>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.phi, a.pi,
-                           a.phi_out, a.pi_out, a.rad_i, a.rad_h, a.ang, a.wave, a);
+    const S* phi = reinterpret_cast<const S*>(a.phi);
+    const S* pi = reinterpret_cast<const S*>(a.pi);
+    S* phi_out = reinterpret_cast<S*>(a.phi_out);
+    S* pi_out = reinterpret_cast<S*>(a.pi_out);
+    S* wave = reinterpret_cast<S*>(a.wave);
+    if (a.kb == 2 && a.split)
+        hipLaunchKernelGGL((lw_step_split_kernel<S, R>), dim3(a.n_strips * a.n_chunks), dim3(2 * WAVE), 0, s, phi, pi,
+                           phi_out, pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
+    else if (a.kb == 2)
+        hipLaunchKernelGGL((lw_step_kernel<S, R, 2>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, phi_out,
+                           pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
     else
-        hipLaunchKernelGGL((lw_step_kernel<R, 1>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, a.phi, a.pi,
-                           a.phi_out, a.pi_out, a.rad_i, a.rad_h, a.ang, a.wave, a);
+        hipLaunchKernelGGL((lw_step_kernel<S, R, 1>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, phi_out,
+                           pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
 }
-void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step(a, s); }
-void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step(a, s); }
+void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step<double>(a, s); }
+void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step<float>(a, s); }
+void launch_step_fp32s(const StepArgs<double>& a, hipStream_t s) { launch_step<float>(a, s); }
 
 // Batched launches: every instance of a batch advances kb steps in one
 // launch.  Tiles are numbered instance by instance; the step and the
@@ -453,7 +676,7 @@ __device__ __forceinline__ void batch_tile(cinst I, cclock clk, int t, int wid, 
     const int chunk = local / ngrp;
     const int strip = (local - chunk * ngrp) * WG_WAVES + wid;
     if (strip < n_strips)
-        step_tile<double, KB>(I->buf[src][0], I->buf[src][1], I->buf[1 - src][0], I->buf[1 - src][1], I->rad_i,
+        step_tile<double, double, KB>(I->buf[src][0], I->buf[src][1], I->buf[1 - src][0], I->buf[1 - src][1], I->rad_i,
                               I->rad_h, I->ang, I->wave, P, strip, chunk, lds);
 }
 

@@ -32,7 +32,8 @@ def delta_of_rstar(rstar, a, M=1.0) -> float:
 class Solver:
     """Lax-Wendroff evolution of (Phi, Pi) for one (a, M, m, s) mode.
 
-    State tensors are complex128 (prec=64) or complex64 (prec=32) of shape
+    State tensors are complex128 (prec=64) or complex64 (prec=32, and prec=48:
+    FP32 storage with FP64 arithmetic) of shape
     (n_theta, n_rstar), r* contiguous, owned by this object and bound to the
     library; ``phi``/``pi`` return the pair that holds the latest state.
     """
@@ -175,25 +176,26 @@ class Solver:
         return check_int(_lib.lib().teuk_get_blocking(self._ctx))
 
     def autotune(self, launches_per_trial=20, cache=None):
-        """Pick the fastest (theta rows per wave, steps per launch) by timing
-        trial launches on the bound state; returns (rows, steps_per_launch).
-        Results of ``step`` are bitwise identical for every choice.  With a
-        cache file (``cache`` or the TEUK_TUNE_CACHE environment variable) a
-        choice found earlier for this grid, precision and GPU model is applied
-        without trials, and a new one is recorded."""
+        """Pick the fastest (theta rows per wave, steps per launch, launch form)
+        by timing trial launches on the bound state; returns (rows,
+        steps_per_launch) and ``get_tiling`` reports the form (order).  Results
+        of ``step`` are bitwise identical for every choice.  With a cache file
+        (``cache`` or the TEUK_TUNE_CACHE environment variable) a choice found
+        earlier for this grid, precision and GPU model is applied without
+        trials, and a new one is recorded."""
         from . import tune_cache
         path = tune_cache.cache_path(cache)
         k_ = tune_cache.key(torch.cuda.get_device_name(self.device), self.prec, self.shape, "step")
         hit = tune_cache.lookup(path, k_)
-        if hit is not None and len(hit) == 2:
-            self.set_tiling(hit[0], 0)
+        if hit is not None and len(hit) in (2, 3):
+            self.set_tiling(hit[0], hit[2] if len(hit) == 3 else 0)
             self.set_blocking(hit[1])
             return hit[0], hit[1]
         r = ctypes.c_int32()
         k = ctypes.c_int32()
         check(_lib.lib().teuk_autotune(self._ctx, int(launches_per_trial), ctypes.byref(r), ctypes.byref(k)),
               self._ctx)
-        tune_cache.store(path, k_, (r.value, k.value))
+        tune_cache.store(path, k_, (r.value, k.value, self.get_tiling()[1]))
         return r.value, k.value
 
     def get_tiling(self):

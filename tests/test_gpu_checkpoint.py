@@ -100,9 +100,10 @@ def test_autotune_cache_reuses_a_choice(tmp_path):
     path = str(tmp_path / "tune.json")
     a = make(dt)
     choice = a.autotune(3, cache=path)
+    form = a.get_tiling()[1]
     a.close()
     k = tune_cache.key(torch.cuda.get_device_name(0), 64, (NTH, NR), "step")
-    assert tune_cache.lookup(path, k) == list(choice)
+    assert tune_cache.lookup(path, k) == list(choice) + [form]
     # a planted entry is applied as it is, without trials
     tune_cache.store(path, k, (5, 1))
     b = make(dt)

@@ -97,7 +97,7 @@ def test_tiling_bitwise_invariant(oracle_mod):
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=3)
     for kb in (1, 2):
         ref = run_gpu(case, phi, pi, 20, rows=1, kb=kb)
-        for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1)):
+        for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1), (1, 2), (5, 2), (64, 2), (4096, 2)):
             got = run_gpu(case, phi, pi, 20, rows=rows, order=order, kb=kb)
             for x, y in zip(got, ref):
                 assert np.array_equal(x, y), (rows, order, kb)
@@ -116,6 +116,10 @@ def test_temporal_blocking_bitwise(oracle_mod, idx, prec):
         got = run_gpu(case, phi, pi, n, prec=prec, rows=rows, kb=2)
         for x, y in zip(got, ref):
             assert np.array_equal(x, y), (case["name"], n, rows)
+        # the fused pair on two wavefronts
+        got = run_gpu(case, phi, pi, n, prec=prec, rows=rows or 16, order=2, kb=2)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), (case["name"], n, rows, "pair")
 
 
 @pytest.mark.parametrize("robs_index", [59, 60, 61, 119, 120])
@@ -247,19 +251,21 @@ def test_nonfinite_is_reported():
     s.close()
 
 
-def test_fp32_waveform_error(oracle_mod):
-    # FP32 storage and arithmetic vs the FP64 oracle on the Schwarzschild pulse
+@pytest.mark.parametrize("prec", [32, 48], ids=["fp32", "fp32s"])
+def test_fp32_waveform_error(oracle_mod, prec):
+    # FP32 storage (with FP32 or FP64 arithmetic) vs the FP64 oracle on the
+    # Schwarzschild pulse
     case = dict(name="c1", nr=256, nth=64, rmin=-50.0, rmax=150.0, a=0.0, m=2, s=-2, robs=100.0)
     n = 2000
     case["dt"] = _dt(oracle_mod, case, n)
     phi, pi = inputs.pulse(256, 64, -50.0, 150.0, 2, 20.0, 4.0, inputs.seeded_amplitude(1))
     # read further in so that the pulse reaches the observer within the run
     case["robs"] = 30.0
-    gp, gq, gw = run_gpu(case, phi, pi, n, prec=32)
+    gp, gq, gw = run_gpu(case, phi, pi, n, prec=prec)
     op, oq, ow = run_oracle(oracle_mod, case, phi, pi, n)
     err_w = rel(gw, ow)
     err_s = rel(gp, op)
-    print(f"[gpu] fp32 waveform rel err {err_w:.3e}, state {err_s:.3e}", flush=True)
+    print(f"[gpu] prec {prec} waveform rel err {err_w:.3e}, state {err_s:.3e}", flush=True)
     assert err_w <= 1e-5, err_w
 
 
@@ -292,7 +298,8 @@ def test_autotune_keeps_state_and_results(oracle_mod):
     s.close()
 
 
-def test_fp32_waveform_error_kerr_8192x256(oracle_mod):
+@pytest.mark.parametrize("prec", [32, 48], ids=["fp32", "fp32s"])
+def test_fp32_waveform_error_kerr_8192x256(oracle_mod, prec):
     # FP32 storage and arithmetic on the full Kerr a = 0.9 source grid against
     # the FP64 oracle: smooth seeded data, 300 steps, waveform at r* = 20
     nr, nth, rmin, rmax, a, m = 8192, 256, -100.0, 400.0, 0.9, 2
@@ -301,10 +308,10 @@ def test_fp32_waveform_error_kerr_8192x256(oracle_mod):
     n = 300
     phi, pi = inputs.smooth_random_state(nr, nth, rmin, rmax, seed=23)
     print(f"[gpu] fp32 8192x256 n={n}", flush=True)
-    gp, gq, gw = run_gpu(case, phi, pi, n, prec=32)
+    gp, gq, gw = run_gpu(case, phi, pi, n, prec=prec)
     op, oq, ow = run_oracle(oracle_mod, case, phi, pi, n)
     err_w = rel(gw, ow)
-    print(f"[gpu] fp32 8192x256 waveform rel err {err_w:.3e}, state {rel(gp, op):.3e}", flush=True)
+    print(f"[gpu] prec {prec} 8192x256 waveform rel err {err_w:.3e}, state {rel(gp, op):.3e}", flush=True)
     assert err_w <= 1e-5, err_w
 
 
@@ -322,6 +329,7 @@ def _random_cases(k=16, seed=2027):
                     kb=int(rng.integers(1, 3)))
         if rng.integers(0, 2):
             case.update(r0=float(rng.uniform(6.0, 12.0)), amp=float(rng.uniform(0.5, 2.0)))
+        case["order"] = 2 * (i % 2)   # every other case: a fused pair on two wavefronts
         out.append(case)
     return out
 
@@ -331,7 +339,28 @@ def test_parity_seeded_random_configurations(oracle_mod, case):
     case = dict(case, dt=_dt(oracle_mod, case, 1000))
     print(f"[gpu] random parity {case}", flush=True)
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=int(case["name"][4:]) + 100)
-    gp, gq, gw = run_gpu(case, phi, pi, case["n"], rows=case["rows"], kb=case["kb"])
+    gp, gq, gw = run_gpu(case, phi, pi, case["n"], rows=case["rows"], kb=case["kb"], order=case["order"])
     op, oq, ow = run_oracle(oracle_mod, case, phi, pi, case["n"])
     assert rel(gp, op) <= TOL64 and rel(gq, oq) <= TOL64, (rel(gp, op), rel(gq, oq))
     assert rel(gw, ow) <= TOL64, rel(gw, ow)
+
+
+def test_fp32_storage_fp64_arithmetic_tilings(oracle_mod):
+    # FP32 storage with FP64 arithmetic: bitwise equal across tilings and
+    # launch forms at fixed steps per launch; one or two steps per launch
+    # differ only by where the state is rounded to FP32
+    case = dict(SMALL[4])
+    case["dt"] = _dt(oracle_mod, case)
+    phi, pi = inputs.random_state(case["nr"], case["nth"], seed=48)
+    for kb in (1, 2):
+        ref = run_gpu(case, phi, pi, 20, prec=48, rows=1, kb=kb)
+        for rows, order in ((3, 1), (16, 0), (64, 0)) + (((5, 2), (4096, 2)) if kb == 2 else ()):
+            got = run_gpu(case, phi, pi, 20, prec=48, rows=rows, order=order, kb=kb)
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y), (rows, order, kb)
+        if kb == 1:
+            one = ref
+    for x, y in zip(ref, one):
+        assert rel(x, y) <= 1e-6
+    op, oq, ow = run_oracle(oracle_mod, case, phi, pi, 20)
+    assert rel(ref[2], ow) <= 1e-6
