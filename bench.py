@@ -54,7 +54,9 @@ def measured_traffic(prec):
             return None
         e = rec["fp%d" % prec]
         return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],
-                "write_bytes": e["write_bytes"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+                "write_bytes": e["write_bytes"],
+                "source": (f"{os.path.relpath(TRAFFIC_FILE, ROOT)}: rocprofv3 counters taken on the kernel code of "
+                           f"commit {rec.get('kernel_commit', '?')} (same code hash as this build); not this run's")}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -496,10 +498,13 @@ def fp32_error_full_length():
     dt = golden[0]["dt"] if golden else suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, n)
     w32 = run(W, n, robs, 32, dt)
     w64 = run(W, n, robs, 64, dt)
-    rec = {"steps": n, "rstar_obs": robs, "dt": dt, "vs_gpu_fp64": errs(w32, w64), "bound": 1e-5}
+    w32s = run(W, n, robs, 48, dt)
+    rec = {"steps": n, "rstar_obs": robs, "dt": dt, "vs_gpu_fp64": errs(w32, w64), "bound": 1e-5,
+           "fp32_storage_fp64_math": {"vs_gpu_fp64": errs(w32s, w64)}}
     if golden:
         sl = np.ix_(golden[2], golden[3])
         rec["vs_oracle_fp64"] = errs(w32[sl], golden[1])
+        rec["fp32_storage_fp64_math"]["vs_oracle_fp64"] = errs(w32s[sl], golden[1])
         rec["gpu_fp64_vs_oracle"] = errs(w64[sl], golden[1])
         rec["oracle_sample"] = f"{len(golden[2])} steps x {len(golden[3])} theta rows"
     out[W.name] = rec
@@ -508,7 +513,9 @@ def fp32_error_full_length():
     dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, n)
     w32 = run(W, n, robs, 32, dt)
     w64 = run(W, n, robs, 64, dt)
-    out[W.name] = {"steps": n, "rstar_obs": robs, "dt": dt, "vs_gpu_fp64": errs(w32, w64), "bound": 1e-5}
+    w32s = run(W, n, robs, 48, dt)
+    out[W.name] = {"steps": n, "rstar_obs": robs, "dt": dt, "vs_gpu_fp64": errs(w32, w64), "bound": 1e-5,
+                   "fp32_storage_fp64_math": {"vs_gpu_fp64": errs(w32s, w64)}}
     return out
 
 
@@ -583,6 +590,53 @@ def fp32_error():
     return out
 
 
+def cpu_model():
+    """The host CPU's model name and logical core count, as the kernel reports them."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
+_CPU_FULL_RUN = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_0909_4039_amd import inputs, workloads
+W = workloads.SCHWARZSCHILD_PULSE
+oracle.build()
+dt = oracle.stable_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
+                       inputs.seeded_amplitude(W.pulse["seed"]))
+o = oracle.Oracle(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, rstar_obs=W.rstar_obs)
+o.run(phi, pi, 10)
+t = time.perf_counter()
+o.run(phi, pi, W.steps)
+el = time.perf_counter() - t
+print(json.dumps({{"workload": W.name, "steps": W.steps, "seconds": el,
+                  "updates_per_s": W.nr * W.nth * W.steps / el, "threads": oracle.threads()}}))
+"""
+
+
+def cpu_full_run_small():
+    """The oracle over the whole Schwarzschild pulse workload (256 x 64, its
+    2000 steps, waveform recorded), on one thread in a child process (a grid
+    this small gains nothing from more): a full run beside the sampled one."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _CPU_FULL_RUN.format(root=ROOT)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(W, seconds):
     import numpy as np
     import oracle
@@ -626,7 +680,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W, args.cpu_seconds)
+        cpu["host"] = cpu_model()
         cpu["single_thread"] = cpu_baseline_single_thread(args.cpu_seconds / 2)
+        cpu["full_run"] = cpu_full_run_small()
     import torch
     ms, dt, kb, tiling = time_solver(W, 64, args.steps, args.warmup)
     ms_step = ms / args.steps
@@ -649,13 +705,15 @@ def main():
         "config": {"workload": W.name, "n_rstar": W.nr, "n_theta": W.nth, "rstar": [W.rstar_min, W.rstar_max],
                    "a": W.a, "m": W.m, "s": W.s, "r0": W.r0, "rstar_obs": W.rstar_obs, "dt": dt,
                    "initial_data": "zero, source on", "steps_per_launch": kb,
-                   "rows_per_wave": tiling[0]},
+                   "rows_per_wave": tiling[0],
+                   "launch_form": "pair of wavefronts per tile" if tiling[1] == 2 else "one wavefront per tile"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK,
                      # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE), or None
                      "traffic": (lambda t: t["bytes_per_launch"] if t else None)(measured_traffic(64)),
                      "traffic_detail": measured_traffic(64),
-                     "kernel": f"lw_step_kernel<double, {kb}>",
+                     "kernel": ("lw_step_split_kernel<double, double>" if (kb == 2 and tiling[1] == 2)
+                                else f"lw_step_kernel<double, double, {kb}>"),
                      "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
         # update rate expressed as the bandwidth an unblocked step would need
         "effective": {"update_bandwidth_GBs": BYTES_PER_UPDATE[64] * ups / 1e9,
@@ -664,7 +722,7 @@ def main():
     # the kernel without temporal blocking, for comparison: one step per launch
     ms1, rows1 = time_single_step(W, 64)
     out["roofline"]["single_step_kernel"] = {
-        "kernel": "lw_step_kernel<double, 1>", "rows_per_wave": rows1, "launch_ms": ms1,
+        "kernel": "lw_step_kernel<double, double, 1>", "rows_per_wave": rows1, "launch_ms": ms1,
         "achieved": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / 1e9,
         "frac": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / HBM_PEAK,
         "note": "one step per launch: slower per step than the two-step launch above, which is what runs"}
