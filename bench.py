@@ -187,7 +187,7 @@ def time_adjoint(steps=None):
     # hence g and dL/da, is zero: see the adjoint FD test for values)
     del dLda
     spin = {"ms": spin_s * 1e3, "over_forward": spin_s / fwd, "checkpoint_interval": ck,
-            "stored_states": int(np.ceil(n / ck)) + ck + 3}
+            "stored_states": int(np.ceil(n / ck)) + ck + 1}
     del p0, q0
     # the same grid and run with an inspiralling source (mass ratio 1e-4):
     # forward with the orbit table, and the reverse sweep that also returns

@@ -238,9 +238,12 @@ int teuk_adjoint_moving(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, i
  * for p +- h; error O(h^2), plus rounding of order eps/h).  The forward run
  * from (phi0, pi0) at t_start keeps every C-th state (checkpoint_interval
  * C; 0 picks ceil(sqrt(n_steps))); the reverse sweep recomputes each
- * segment of C states from its checkpoint.  So memory is ceil(n/C) + C + 3
- * states, and the cost is about five forward runs.  Contractions and their
- * sum follow fixed orders (results repeat bit for bit).
+ * segment of C states from its checkpoint, and one launch per reverse step
+ * evaluates both perturbed steps on the same u^k and contracts their
+ * difference with lambda^{k+1} without storing either.  So memory is
+ * ceil(n/C) + C + 1 states, and the cost is about five and a half forward
+ * runs.  Contractions and their sum follow fixed orders (results repeat bit
+ * for bit).
  *   dL_dwave: device, (n_steps + 1) x n_theta complex128, as teuk_adjoint.
  *   phi0, pi0: device, n_theta x n_rstar complex128, the initial data (read).
  *   workspace: device, teuk_param_gradient_workspace_bytes(ctx, n_steps, C)

@@ -529,44 +529,4 @@ void launch_slot_sum(const double* slots, int64_t n_slots, double* out, hipStrea
     hipLaunchKernelGGL(slot_sum_kernel, dim3(1), dim3(256), 0, s, slots, n_slots, out);
 }
 
-// Parameter gradients: Re sum conj(lambda) (v+ - v-) over Phi and Pi, the
-// contraction of the adjoint of u^{k+1} with the difference of two steps
-// of u^k under perturbed parameters.  Each of DOT_BLOCKS blocks sums a fixed
-// grid-stride share and a fixed tree into part[block]; dot_final_kernel
-// sums the parts in block order into *out, so the result repeats bit for bit.
-constexpr int DOT_BLOCKS = 512;
-__global__ __launch_bounds__(256) void param_dot_kernel(const double* __restrict__ lp, const double* __restrict__ lq,
-                                                         const double* __restrict__ pp, const double* __restrict__ pq,
-                                                         const double* __restrict__ mp, const double* __restrict__ mq,
-                                                         int64_t n_real, double* __restrict__ part) {
-    __shared__ double red[256];
-    const int t = threadIdx.x;
-    double s = 0.0;
-    // real view: Re(conj(l) d) = l.re d.re + l.im d.im, a plain dot over the doubles
-    for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < n_real; i += (int64_t)DOT_BLOCKS * 256) {
-        s = fma(lp[i], pp[i] - mp[i], s);
-        s = fma(lq[i], pq[i] - mq[i], s);
-    }
-    red[t] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) part[blockIdx.x] = red[0];
-}
-__global__ __launch_bounds__(64) void dot_final_kernel(const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < DOT_BLOCKS; ++b) s += part[b];
-        out[0] = s;
-    }
-}
-void launch_param_dot(const double* lp, const double* lq, const double* pp, const double* pq, const double* mp,
-                      const double* mq, int64_t n_real, double* part, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(param_dot_kernel, dim3(DOT_BLOCKS), dim3(256), 0, s, lp, lq, pp, pq, mp, mq, n_real, part);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, s, part, out);
-}
-int param_dot_parts() { return DOT_BLOCKS; }
-
 }  // namespace teuk

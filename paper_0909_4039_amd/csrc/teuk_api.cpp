@@ -1002,10 +1002,11 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
 
 // ------------------------------------------------------- parameter gradients
 
-// One FP64 step of x (its tables, source and tiling; one step per launch)
-// from (ip, iq) into (op, oq) at time t, with a fixed-orbit source; records
-// no waveform and leaves x's bound state, step count and time alone.
-static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t) {
+// Launch arguments of one FP64 step of x (its tables, source and tiling; one
+// step per launch) from (ip, iq) into (op, oq) at time t, with a
+// fixed-orbit source; no waveform is recorded.
+static StepArgs<double> step_args_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq,
+                                     double t) {
     const Geometry& g = x->geo;
     StepArgs<double> a = step_args<double>(x);
     a.kb = 1;
@@ -1025,30 +1026,36 @@ static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, 
     a.pi = iq;
     a.phi_out = op;
     a.pi_out = oq;
-    launch_step_fp64(a, x->stream);
+    return a;
+}
+
+// One FP64 step of x from (ip, iq) into (op, oq) at time t (see
+// step_args_at); leaves x's bound state, step count and time alone.
+static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t) {
+    launch_step_fp64(step_args_at(x, ip, iq, op, oq, t), x->stream);
     HIP_TRY(x, hipGetLastError());
     return TEUK_OK;
 }
 
 // Workspace of a parameter gradient: two adjoint pairs, the reverse step's
-// gradient slots, ceil(n / C) checkpoints, C - 1 segment states, two
-// perturbed-step outputs, the dot product's block parts and one double per
-// step.  A state is Phi and Pi, complex128 [nth][nr] each.
+// gradient slots, ceil(n / C) checkpoints, C - 1 segment states, the fused
+// contraction's per-tile parts (at most one per strip and theta row) and
+// one double per step.  A state is Phi and Pi, complex128 [nth][nr] each.
 struct ParamLayout {
-    int64_t state, lam, slots, ckpt, seg, pert, parts, res, total, n_ckpt;
+    int64_t state, lam, slots, ckpt, seg, parts, res, total, n_ckpt;
 };
 static ParamLayout param_layout(const teuk_ctx* c, int64_t n, int64_t C) {
     ParamLayout L;
     const int64_t npts = c->geo.nr * c->geo.nth;
+    const int64_t strips1 = (c->geo.nr + WAVE - 3) / (WAVE - 2);   // strips of a one-step launch
     L.state = round256(2 * npts * 16);
     L.n_ckpt = n > 0 ? (n + C - 1) / C : 1;
     L.lam = 0;
     L.slots = L.lam + 2 * L.state;
     L.ckpt = L.slots + round256(adjoint_slots_max(c->geo) * 3 * 8);
     L.seg = L.ckpt + L.n_ckpt * L.state;
-    L.pert = L.seg + std::max<int64_t>(C - 1, 0) * L.state;
-    L.parts = L.pert + 2 * L.state;
-    L.res = L.parts + round256((int64_t)param_dot_parts() * 8);
+    L.parts = L.seg + std::max<int64_t>(C - 1, 0) * L.state;
+    L.res = L.parts + round256(strips1 * c->geo.nth * 8);
     L.total = L.res + round256(std::max<int64_t>(n, 1) * 8);
     return L;
 }
@@ -1061,7 +1068,8 @@ static int64_t default_interval(int64_t n) {
 // The checkpointed sweep: forward from u^0 keeping every C-th state, then
 // segment by segment from the last, recompute the segment's states from its
 // checkpoint, and for each step k (descending) contract lambda^{k+1} with
-// step_{p+h}(u^k) - step_{p-h}(u^k) and take the reverse step to lambda^k.
+// step_{p+h}(u^k) - step_{p-h}(u^k) (one fused launch, lw_pdot_kernel, that
+// does not store the two steps) and take the reverse step to lambda^k.
 static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double alpha, const double* g, int64_t n,
                        double t_start, const double* phi0, const double* pi0, int64_t C, char* ws,
                        std::vector<double>& res, const double** lam0) {
@@ -1074,17 +1082,18 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
     double* slots = state(L.slots);
     auto ckpt = [&](int64_t j) { return state(L.ckpt + j * L.state); };
     auto seg = [&](int64_t j, int64_t i) { return i == 0 ? ckpt(j) : state(L.seg + (i - 1) * L.state); };
-    double* X = state(L.pert);
-    double* Y = state(L.pert + L.state);
     double* parts = state(L.parts);
     double* dres = state(L.res);
     const double dt = c->dt;
     // forward pass, keeping u^{jC}
     HIP_TRY(c, hipMemcpyAsync(ckpt(0), phi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(pi_of(ckpt(0)), pi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
+    // forward states between checkpoints alternate between the two adjoint
+    // pairs, which are not in use yet
+    double* tmp[2] = {lam[0], lam[1]};
     double* cur = ckpt(0);
     for (int64_t k = 0; k + 1 < n; ++k) {   // u^n itself is not needed
-        double* next = ((k + 1) % C == 0) ? ckpt((k + 1) / C) : (cur == X ? Y : X);
+        double* next = ((k + 1) % C == 0) ? ckpt((k + 1) / C) : (cur == tmp[0] ? tmp[1] : tmp[0]);
         int rc = step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt);
         if (rc != TEUK_OK) return rc;
         cur = next;
@@ -1107,11 +1116,13 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
         for (int64_t k = k1 - 1; k >= k0; --k) {
             double* u = seg(j, k - k0);
             const double t = t_start + double(k) * dt;
-            int rc = step_at(xp, u, pi_of(u), X, pi_of(X), t);
-            if (rc == TEUK_OK) rc = step_at(xm, u, pi_of(u), Y, pi_of(Y), t);
-            if (rc != TEUK_OK) return rc;
-            launch_param_dot(lam[li], pi_of(lam[li]), X, pi_of(X), Y, pi_of(Y), 2 * npts, parts, dres + k,
-                             c->stream);
+            PdotArgs pd;
+            pd.s[0] = step_args_at(xp, u, pi_of(u), nullptr, nullptr, t);
+            pd.s[1] = step_args_at(xm, u, pi_of(u), nullptr, nullptr, t);
+            pd.lp = lam[li];
+            pd.lq = pi_of(lam[li]);
+            pd.part = parts;
+            launch_param_pdot(pd, u, pi_of(u), dres + k, c->stream);
             HIP_TRY(c, hipGetLastError());
             adjoint_launch_args(c, a, 1, k + 1, t_start, true);
             a.lp = lam[li];

@@ -225,9 +225,17 @@ void launch_fill_zero(double* x, int64_t n, hipStream_t s);
 void launch_slot_sum(const double* slots, int64_t n_slots, double* out, hipStream_t s);
 void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_t top, double* out,
                             hipStream_t s);
-void launch_param_dot(const double* lp, const double* lq, const double* pp, const double* pq, const double* mp,
-                      const double* mq, int64_t n_real, double* part, double* out, hipStream_t s);
-int param_dot_parts();
+// Fused parameter-gradient contraction (lw_pdot_kernel): s[0] and s[1] are
+// one-step launches of the contexts built at p + h and p - h on the same
+// grid and tiling; part holds pdot_parts(s[0]) doubles.
+struct PdotArgs {
+    StepArgs<double> s[2];
+    const double* lp;   // lambda^{k+1}: interleaved complex [nth][nr]
+    const double* lq;
+    double* part;
+};
+int64_t pdot_parts(const StepArgs<double>& a);
+void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s);
 void launch_watch_fp64(const double* x, int64_t n, double lim, int64_t tag, unsigned long long* found,
                        hipStream_t s);
 void launch_watch_fp32(const float* x, int64_t n, float lim, int64_t tag, unsigned long long* found,

@@ -286,6 +286,69 @@ __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __rest
     }
 }
 
+// The tile's share of the coefficient tables, into its wavefront's LDS
+// slice (see step_tile).  src_here: a column of this lane meets a nonzero
+// source value.
+template <typename R, int KB, typename P>
+__device__ __forceinline__ void tile_tables(const R* __restrict__ rad_i, const R* __restrict__ rad_h, const P& A,
+                                            int strip, FwdLds<R, KB>* lds, bool& src_here) {
+    constexpr int SO = WAVE - 2 * KB;   // valid output columns per strip
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int nr = A.nr();
+    const int c = strip * SO - KB + lane;
+    // Lanes outside the grid read a clamped column: they feed only the
+    // half points beyond the r* boundaries, whose outputs are the Dirichlet
+    // zeros or are never stored.
+    const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
+    // radial numerators of this wavefront's columns (CRR and WBN, which
+    // multiply r* differences only, carry the 1/dr* of those differences)
+    const R idr = R(2) * A.inv_dr();   // 2/dr*: the stage sees doubled differences (see stage())
+    R (*srad)[N_RAD_FWD][WAVE] = lds->rad;
+    for (int k = 0; k < 2 * N_RAD_FWD; ++k) {
+        const int loc = k / N_RAD_FWD, f = k % N_RAD_FWD;
+        const R v = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
+        srad[loc][f][lane] = (f == R_CRR || f == R_WBN) ? v * idr : v;
+    }
+    // source radial factor of each fused step at its predictor (half point,
+    // t^{n+k}) and corrector (integer point, t^{n+k} + dt/2): the table's
+    // for a fixed orbit, exp(-(r* - r*0(t))^2 / (2 sr^2)) for a moving one
+    src_here = false;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        for (int loc = 0; loc < 2; ++loc) {
+            R v;
+            if (A.moving()) {
+                const R x = fma((R)c + (loc == 0 ? R(0.5) : R(0)), A.dr(), A.rmin()) - A.rs0(2 * k + loc);
+                v = exp((-x * x) / A.two_sr2());
+            } else {
+                v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * A.stride() + cu];
+            }
+            lds->src[k][loc][lane] = v * (loc == 0 ? R(2) : R(4));   // 2T predictor, 4T corrector
+            src_here = src_here || (v != R(0) && c >= 0 && c < nr);
+        }
+}
+
+// The stage constants of a tile whose tables sit in `lds`; c is the lane's
+// column.
+template <typename R, int KB, typename P>
+__device__ __forceinline__ Consts<R> tile_consts(const R* __restrict__ ang, const P& A, FwdLds<R, KB>* lds,
+                                                 int lane, int c) {
+    const int nr = A.nr();
+    const R idr = R(2) * A.inv_dr();   // 2/dr* (see stage())
+    Consts<R> K;
+    K.ang = ang;
+    K.srad = lds->rad;
+    K.ssrc = lds->src;
+    K.lane = lane;
+    K.nth = A.nth();
+    K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
+    K.idr = idr;
+    K.qdt = R(0.25) * A.dt();
+    K.hdt = A.hdt();
+    K.m2ma_idr = A.m2ma() * idr;
+    return K;
+}
+
 // KB Lax-Wendroff steps over one tile (one wavefront's strip of r* columns
 // and its chunk of theta rows), the work unit of both the single-mode and
 // the batched kernel.  The intermediate states never leave registers.  Each
@@ -305,52 +368,15 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ phi, const S* __
     const int lane = threadIdx.x & (WAVE - 1);
     const int nr = A.nr(), nth = A.nth();
     const int c = strip * SO - KB + lane;
-    // Lanes outside the grid read a clamped column: they feed only the
-    // half points beyond the r* boundaries, whose outputs are the Dirichlet
-    // zeros or are never stored.
     const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
-    // radial numerators of this wavefront's columns (CRR and WBN, which
-    // multiply r* differences only, carry the 1/dr* of those differences)
-    const R idr = R(2) * A.inv_dr();   // 2/dr*: the stage sees doubled differences (see stage())
-    R (*srad)[N_RAD_FWD][WAVE] = lds->rad;
-    for (int k = 0; k < 2 * N_RAD_FWD; ++k) {
-        const int loc = k / N_RAD_FWD, f = k % N_RAD_FWD;
-        const R v = (loc == 0 ? rad_h : rad_i)[(int64_t)f * A.stride() + cu];
-        srad[loc][f][lane] = (f == R_CRR || f == R_WBN) ? v * idr : v;
-    }
-    // source radial factor of each fused step at its predictor (half point,
-    // t^{n+k}) and corrector (integer point, t^{n+k} + dt/2): the table's
-    // for a fixed orbit, exp(-(r* - r*0(t))^2 / (2 sr^2)) for a moving one
-    bool src_here = false;   // a column of this lane meets the source
-#pragma unroll
-    for (int k = 0; k < KB; ++k)
-        for (int loc = 0; loc < 2; ++loc) {
-            R v;
-            if (A.moving()) {
-                const R x = fma((R)c + (loc == 0 ? R(0.5) : R(0)), A.dr(), A.rmin()) - A.rs0(2 * k + loc);
-                v = exp((-x * x) / A.two_sr2());
-            } else {
-                v = (loc == 0 ? rad_h : rad_i)[(int64_t)R_GR * A.stride() + cu];
-            }
-            lds->src[k][loc][lane] = v * (loc == 0 ? R(2) : R(4));   // 2T predictor, 4T corrector
-            src_here = src_here || (v != R(0) && c >= 0 && c < nr);
-        }
+    bool src_here;
+    tile_tables<R, KB>(rad_i, rad_h, A, strip, lds, src_here);
     const int j0 = chunk * A.rows();
     const int jend = min(j0 + A.rows(), nth);
     const bool out_lane = (c >= 0) && (c < nr) && lane >= KB && lane <= WAVE - 1 - KB;
     const unsigned boff = cu * (unsigned)(2 * sizeof(S));          // byte offset of this lane's column
     const unsigned soff = (unsigned)max(c, 0) * (unsigned)(2 * sizeof(S));
-    Consts<R> K;
-    K.ang = ang;
-    K.srad = srad;
-    K.ssrc = lds->src;
-    K.lane = lane;
-    K.nth = nth;
-    K.keep = ((c == 0) || (c == nr - 1)) ? R(0) : R(1);   // Phi = Pi = 0 on the r* boundary
-    K.idr = idr;
-    K.qdt = R(0.25) * A.dt();
-    K.hdt = A.hdt();
-    K.m2ma_idr = A.m2ma() * idr;
+    const Consts<R> K = tile_consts<R, KB>(ang, A, lds, lane, c);
     // recorder: the strip holding columns iobs and iobs+1 among its lanes
     const bool rec = (A.iobs() / SO == strip);
     const int wl = A.iobs() - strip * SO + KB;
@@ -615,6 +641,136 @@ static void launch_step(const StepArgs<R>& a, hipStream_t s) {
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step<double>(a, s); }
 void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step<float>(a, s); }
 void launch_step_fp32s(const StepArgs<double>& a, hipStream_t s) { launch_step<float>(a, s); }
+
+// Parameter gradients: the contraction of the adjoint state lambda^{k+1}
+// with the difference of two forward steps of u^k, one under coefficients
+// built at p + h and one at p - h,
+//   Re sum conj(lambda) (step_{p+h}(u) - step_{p-h}(u))   over Phi and Pi,
+// without writing the two stepped states.  A tile runs both steps on the
+// same input rows (two stage pipelines, each with its own tables, one step
+// each) and adds lambda times the difference of their outputs.  The
+// differences are those of the step kernel's outputs bit for bit; the sum
+// runs over lanes, then tiles, in fixed orders.
+template <bool EDGE>
+__device__ __forceinline__ void march_pdot(const double* __restrict__ phi, const double* __restrict__ pi,
+                                           const double* __restrict__ lp, const double* __restrict__ lq,
+                                           const ArgParams<double>& Ap, const ArgParams<double>& Am,
+                                           const Consts<double>& Kp, const Consts<double>& Km, int j0, int jend,
+                                           unsigned boff, bool out_lane, double& acc) {
+    const int nr = Ap.nr(), nth = Ap.nth();
+    const cx<double> zero = {0.0, 0.0};
+    Pipe<double> sp, sm;
+    pipe_init(sp, j0, jend, nth);
+    pipe_init(sm, j0, jend, nth);
+    const int Ls = max(sp.olo - 2, 0);   // first input row
+    const int Le = jend + 1;             // last iteration: C of row jend - 1
+    // Input rows and the lambda rows of an iteration's outputs (Pi at row
+    // L - 2, Phi at row L - 1) are in flight two iterations ahead, in the
+    // buffer set of the iteration's parity.
+    struct Rows {
+        cx<double> p, q, lq, lp;
+    };
+    auto request = [&](int L, Rows& b) {
+        b.p = b.q = b.lq = b.lp = zero;
+        if (L < sp.ihi) {
+            b.p = ld_row_once(phi, (int64_t)L * nr, boff);
+            b.q = ld_row_once(pi, (int64_t)L * nr, boff);
+        }
+        if (L - 2 >= sp.olo && L - 2 < sp.ohi) b.lq = ld_row_once(lq, (int64_t)(L - 2) * nr, boff);
+        if (L - 1 >= sp.olo && L - 1 < sp.ohi) b.lp = ld_row_once(lp, (int64_t)(L - 1) * nr, boff);
+    };
+    Rows ra, rb;
+    request(Ls, ra);
+    if (Ls + 1 <= Le) request(Ls + 1, rb);
+    double* const nowave = nullptr;
+    auto iter = [&](int L, Rows& b) {
+        if (L > Le) return;
+        const Rows cur = b;
+        if (L + 2 <= Le) request(L + 2, b);
+        __builtin_amdgcn_sched_barrier(0);
+        cx<double> oPp, oQp, oPm, oQm;
+        bool okP, okQ, okPm, okQm;
+        pipe_iter<EDGE>(sp, Kp, 0, L, cur.p, cur.q, cur.p, cur.q, Ap.ph(0), Ap.ph(1), nowave, -1, 0, j0, jend, 0.0,
+                        oPp, okP, oQp, okQ);
+        pipe_iter<EDGE>(sm, Km, 0, L, cur.p, cur.q, cur.p, cur.q, Am.ph(0), Am.ph(1), nowave, -1, 0, j0, jend, 0.0,
+                        oPm, okPm, oQm, okQm);
+        // Re conj(l) d = l.re d.re + l.im d.im
+        if (okQ && out_lane) {
+            acc = fma(cur.lq.re, oQp.re - oQm.re, acc);
+            acc = fma(cur.lq.im, oQp.im - oQm.im, acc);
+        }
+        if (okP && out_lane) {
+            acc = fma(cur.lp.re, oPp.re - oPm.re, acc);
+            acc = fma(cur.lp.im, oPp.im - oPm.im, acc);
+        }
+    };
+    for (int L = Ls; L <= Le; L += 2) {
+        iter(L, ra);
+        iter(L + 1, rb);
+    }
+}
+
+// One wavefront per tile, four adjacent strips of one theta chunk per
+// workgroup (chunk-major, as lw_step_kernel's order 0); one step per tile.
+// part[chunk * n_strips + strip] receives the tile's sum.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lw_pdot_kernel(
+    const double* __restrict__ phi, const double* __restrict__ pi, PdotArgs B) {
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const StepArgs<double>& A = B.s[0];
+    const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = blk / ngrp;
+    const int strip = (blk - chunk * ngrp) * WG_WAVES + wid;
+    if (strip >= A.n_strips) return;   // wave-uniform; the kernel has no barriers
+    __shared__ FwdLds<double, 1> lds_all[WG_WAVES][2];   // the + and - tables of each wavefront
+    const ArgParams<double> Ap{B.s[0]}, Am{B.s[1]};
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int nr = A.nr, nth = A.nth;
+    const int c = strip * (WAVE - 2) - 1 + lane;
+    const unsigned cu = (unsigned)min(max(c, 0), nr - 1);
+    bool src_p, src_m;
+    tile_tables<double, 1>(B.s[0].rad_i, B.s[0].rad_h, Ap, strip, &lds_all[wid][0], src_p);
+    tile_tables<double, 1>(B.s[1].rad_i, B.s[1].rad_h, Am, strip, &lds_all[wid][1], src_m);
+    const int j0 = chunk * A.rows;
+    const int jend = min(j0 + A.rows, nth);
+    const bool out_lane = (c >= 0) && (c < nr) && lane >= 1 && lane <= WAVE - 2;
+    const unsigned boff = cu * 16u;
+    const Consts<double> Kp = tile_consts<double, 1>(B.s[0].ang, Ap, &lds_all[wid][0], lane, c);
+    const Consts<double> Km = tile_consts<double, 1>(B.s[1].ang, Am, &lds_all[wid][1], lane, c);
+    const bool edge = __ballot(Kp.keep == 0.0 || src_p || src_m) != 0;
+    double acc = 0.0;
+    if (edge)
+        march_pdot<true>(phi, pi, B.lp, B.lq, Ap, Am, Kp, Km, j0, jend, boff, out_lane, acc);
+    else
+        march_pdot<false>(phi, pi, B.lp, B.lq, Ap, Am, Kp, Km, j0, jend, boff, out_lane, acc);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
+    if (lane == 0) B.part[(int64_t)chunk * A.n_strips + strip] = acc;
+}
+
+// Sum of the tiles' parts in a fixed order into *out (one workgroup).
+__global__ __launch_bounds__(256) void pdot_sum_kernel(const double* __restrict__ part, int64_t n,
+                                                       double* __restrict__ out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += 256) s += part[i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[0] = red[0];
+}
+
+int64_t pdot_parts(const StepArgs<double>& a) { return (int64_t)a.n_strips * a.n_chunks; }
+
+void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s) {
+    const StepArgs<double>& a = b.s[0];
+    const int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
+    hipLaunchKernelGGL(lw_pdot_kernel, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, b);
+    hipLaunchKernelGGL(pdot_sum_kernel, dim3(1), dim3(256), 0, s, b.part, pdot_parts(a), out);
+}
 
 // Batched launches: every instance of a batch advances kb steps in one
 // launch.  Tiles are numbered instance by instance; the step and the
