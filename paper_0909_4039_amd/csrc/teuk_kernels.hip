@@ -65,16 +65,32 @@ struct Stage {
     R dw;
 };
 
-template <bool SRC, typename R>
-__device__ __forceinline__ Stage<R> stage(const Rad<R>& q, R gr, const Ang<R>& g, R m2ma_idr, R idr, R tau,
-                                          cx<R> ph, cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df, cx<R> dg) {
+// The coefficients of a stage that depend on the point only: the same for
+// every fused step at that point.
+template <typename R>
+struct Coef {
+    R y2, bi, crr, cti;   // 1/Sigma^2, b/dr*, Re CR/dr*, Im CT
+};
+template <typename R>
+__device__ __forceinline__ Coef<R> coef(const Rad<R>& q, const Ang<R>& g, R idr) {
     R S2 = fma(q.w2, q.w2, -g.a2s2 * q.del);   // Sigma^2
     R y = rsqrt_full(S2);                      // 1/Sigma
-    R y2 = y * y;
-    R bi = (q.w2 * y) * idr;                   // b / dr*, Eq. (6)
+    Coef<R> k;
+    k.y2 = y * y;
+    k.bi = (q.w2 * y) * idr;                   // b / dr*, Eq. (6)
+    k.crr = fma(q.wbn * g.sin2, k.y2, q.crr);
+    k.cti = fma(g.cs, q.del, q.cti0);
+    return k;
+}
+
+template <bool SRC, typename R>
+__device__ __forceinline__ Stage<R> stage(const Coef<R>& k, const Rad<R>& q, R gr, const Ang<R>& g, R m2ma_idr,
+                                          R tau, cx<R> ph, cx<R> f0, cx<R> g0, cx<R> f, cx<R> gm, cx<R> df,
+                                          cx<R> dg) {
+    const R y2 = k.y2, bi = k.bi;
     cx<R> X = {fma(-bi, df.re, gm.re), fma(-bi, df.im, gm.im)};        // Pi - b dPhi
-    cx<R> CR = {fma(q.wbn * g.sin2, y2, q.crr), m2ma_idr * q.w2};     // CR / dr*
-    cx<R> CT = {q.ctr, fma(g.cs, q.del, q.cti0)};
+    cx<R> CR = {k.crr, m2ma_idr * q.w2};                              // CR / dr*
+    cx<R> CT = {q.ctr, k.cti};
     cx<R> V = {q.vr, q.vi};
     cx<R> acc = cfma(CR, df, cfma(V, f, cmul(CT, X)));
     Stage<R> o;
@@ -147,11 +163,12 @@ struct Consts {
 //
 // NB: the input row's values at column c+1 arrive in (p1n, q1n), read from
 // LDS by the caller, instead of by a lane shift.
-template <bool EDGE, bool NB = false, typename R, typename S>
+template <bool EDGE, bool NB = false, int CM = 0, typename R, typename S>
 __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int ks, int L, cx<R> p, cx<R> q,
                                           cx<R> p1n, cx<R> q1n,
                                           cx<R> ph0, cx<R> ph1, S* wave, int64_t wrow, int wl, int rlo,
-                                          int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ) {
+                                          int rhi, R alpha, cx<R>& outP, bool& okP, cx<R>& outQ, bool& okQ,
+                                          Coef<R>* ch = nullptr, Coef<R>* ci = nullptr) {
     const cx<R> zero = {R(0), R(0)};
     const int P = L - 1, Q = L - 2;
     const cx<R> up = st.up, uq = st.uq;
@@ -191,7 +208,11 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
         const Ang<R> g = load_ang(K.ang, L);
         const Rad<R> qh = lds_rad_fwd<R>(K.srad[0], K.lane);   // half point c+1/2
         const R gr = EDGE ? lds_lane(K.ssrc[ks][0], K.lane) : R(0);
-        Stage<R> o = stage<EDGE>(qh, gr, g, K.m2ma_idr, K.idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
+        Coef<R> kc;
+        if constexpr (CM == 2) kc = *ch;
+        else kc = coef(qh, g, K.idr);
+        if constexpr (CM == 1) *ch = kc;
+        Stage<R> o = stage<EDGE>(kc, qh, gr, g, K.m2ma_idr, K.hdt, ph0, pbL, Qb, pbL, Qb, dP, dQ);
         st.hP = o.phi;
         st.hQp = rfma(o.dw, rfma(g.wm, st.pb_prev, g.w0 * pbL), o.pi_part);
         st.hD = o.dw * g.wp;
@@ -210,7 +231,11 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
         const Ang<R> g = load_ang(K.ang, P);
         const Rad<R> qi = lds_rad_fwd<R>(K.srad[1], K.lane);   // integer point c
         const R gr = EDGE ? lds_lane(K.ssrc[ks][1], K.lane) : R(0);
-        Stage<R> o = stage<EDGE>(qi, gr, g, K.m2ma_idr, K.idr, K.qdt, ph1, up, uq, phL, Qh, dhP, dhQ);
+        Coef<R> kc;
+        if constexpr (CM == 2) kc = *ci;
+        else kc = coef(qi, g, K.idr);
+        if constexpr (CM == 1) *ci = kc;
+        Stage<R> o = stage<EDGE>(kc, qi, gr, g, K.m2ma_idr, K.qdt, ph1, up, uq, phL, Qh, dhP, dhQ);
         st.nQp = rfma(o.dw, rfma(g.wm, st.ph_prev, g.w0 * phL), o.pi_part);
         st.nD = o.dw * g.wp;
         outP = EDGE ? K.keep * o.phi : o.phi;
@@ -250,7 +275,23 @@ __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __rest
         pb_q = ld_row_once(pi, (int64_t)(Ls + 1) * nr, boff);
     }
 
-    auto iter = [&](int L, cx<S>& pf_p, cx<S>& pf_q) {
+    // Two fused steps in FP32: the second step at a point takes the point's
+    // coefficients (Coef) from the first step, which formed them two
+    // iterations earlier, through a ring of four slots (the loop is unrolled
+    // four times so that no slot is copied).  The same values, so the same
+    // results; 20 more VGPRs (118, still 4 waves per SIMD).  FP64 would
+    // need 40 and spill.
+    constexpr bool CACHE = (KB == 2) && std::is_same<R, float>::value;
+    struct Ring {
+        Coef<R> h, i;
+    };
+    Ring r0, r1, r2, r3;
+    {
+        const Coef<R> z = {R(0), R(0), R(0), R(0)};
+        r0.h = r0.i = r1.h = r1.i = r2.h = r2.i = r3.h = r3.i = z;
+    }
+    // iteration L reads the slot written at L - 2 and writes its own
+    auto iter = [&](int L, cx<S>& pf_p, cx<S>& pf_q, Ring& rg, Ring& nw) {
         if (L > Le) return;
         cx<R> p = cvt<R>(pf_p), q = cvt<R>(pf_q);
         if (L + 2 < st[0].ihi && L + 2 <= Le) {
@@ -265,8 +306,15 @@ __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __rest
             cx<R> oP, oQ;
             bool okP, okQ;
             const cx<R> ph0 = A.ph(2 * k), ph1 = A.ph(2 * k + 1);
-            pipe_iter<EDGE>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend,
-                            A.alpha(), oP, okP, oQ, okQ);
+            if constexpr (!CACHE)
+                pipe_iter<EDGE>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl, j0, jend,
+                                A.alpha(), oP, okP, oQ, okQ);
+            else if (k == 0)
+                pipe_iter<EDGE, false, 1>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl,
+                                          j0, jend, A.alpha(), oP, okP, oQ, okQ, &nw.h, &nw.i);
+            else
+                pipe_iter<EDGE, false, 2>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl,
+                                          j0, jend, A.alpha(), oP, okP, oQ, okQ, &rg.h, &rg.i);
             if (k == KB - 1) {
                 if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, cvt<S>(oQ));
                 if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, cvt<S>(oP));
@@ -279,10 +327,19 @@ __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __rest
             }
         }
     };
-    // unrolled twice so that the carried values alternate between register sets
-    for (int L = Ls; L <= Le; L += 2) {
-        iter(L, pa_p, pa_q);
-        iter(L + 1, pb_p, pb_q);
+    // unrolled so that the carried values alternate between register sets
+    if constexpr (CACHE) {
+        for (int L = Ls; L <= Le; L += 4) {
+            iter(L, pa_p, pa_q, r2, r0);
+            iter(L + 1, pb_p, pb_q, r3, r1);
+            iter(L + 2, pa_p, pa_q, r0, r2);
+            iter(L + 3, pb_p, pb_q, r1, r3);
+        }
+    } else {
+        for (int L = Ls; L <= Le; L += 2) {
+            iter(L, pa_p, pa_q, r0, r0);
+            iter(L + 1, pb_p, pb_q, r1, r1);
+        }
     }
 }
 
@@ -426,11 +483,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     // Every row access of a workgroup is one contiguous 4 KiB (FP64) span.
     // Block order (a tuning choice): chunk-major lets the groups that run
-    // together on an XCD touch neighbouring columns of the same rows;
-    // group-major keeps a strip group's chunks together so their halo rows
-    // are served by L2.
+    // together touch neighbouring columns of the same rows; group-major
+    // keeps a strip group's chunks together so their halo rows are served
+    // by L2.  Blocks take tiles in dispatch order, which deals consecutive
+    // blocks to the 8 XCDs in turn: all XCDs then stream the same rows,
+    // and the partial last chunk's cheap tiles come last.  Giving each XCD
+    // a contiguous range of tiles instead measured the same on 32768 x 1024
+    // and up to 17 % slower on 8192 x 256 at small chunks.
     const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = (int)blockIdx.x;
     int chunk, grp;
     if (A.order == 0) {  // chunk-major: concurrent groups read the same rows
         chunk = blk / ngrp;
@@ -718,7 +779,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const StepArgs<double>& A = B.s[0];
     const int ngrp = (A.n_strips + WG_WAVES - 1) / WG_WAVES;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = (int)blockIdx.x;   // dispatch order, as lw_step_kernel
     const int chunk = blk / ngrp;
     const int strip = (blk - chunk * ngrp) * WG_WAVES + wid;
     if (strip >= A.n_strips) return;   // wave-uniform; the kernel has no barriers
