@@ -45,20 +45,58 @@ def kernel_code_hash():
     return h.hexdigest()
 
 
-def measured_traffic(prec):
-    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they
+def measured_traffic(prec, rows, order):
+    """HBM bytes per launch of the two-step launch at this tiling (theta rows
+    per wave, launch form) from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they
     were taken on the current kernel code (else None)."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_code_sha256") != kernel_code_hash():
             return None
-        e = rec["fp%d" % prec]
+        e = rec["fp%d" % prec]["%d:%d" % (rows, order)]
         return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],
                 "write_bytes": e["write_bytes"],
                 "source": (f"{os.path.relpath(TRAFFIC_FILE, ROOT)}: rocprofv3 counters taken on the kernel code of "
-                           f"commit {rec.get('kernel_commit', '?')} (same code hash as this build); not this run's")}
+                           f"commit {rec.get('kernel_commit', '?')} (same code hash as this build) at {rows} rows "
+                           f"per wave, launch form {order}; not this run's")}
     except (OSError, KeyError, ValueError):
         return None
+
+
+# Two-step tilings (theta rows per wave, launch form: 0 one wavefront per
+# tile, 2 a pair) that --tiling-sweep times, and whose HBM counters the
+# traffic record holds: the autotuner's usual choices on 32768 x 1024.
+SWEEP_TILINGS = {64: [(64, 0), (96, 0), (128, 0), (192, 0), (256, 0), (64, 2), (96, 2)],
+                 32: [(48, 0), (64, 0), (96, 0), (128, 0), (192, 0), (48, 2), (64, 2), (96, 2)]}
+
+
+def tiling_sweep(W, steps, warmup):
+    """Milliseconds per two-step launch of the largest workload at each of
+    SWEEP_TILINGS (no autotuning), FP64 and FP32."""
+    import torch
+    from paper_0909_4039_amd.solver import Solver, suggest_dt
+    dt = suggest_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+    out = {}
+    for prec, tilings in SWEEP_TILINGS.items():
+        s = Solver(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, prec=prec)
+        s.set_source(W.r0, W.amp)
+        s.set_blocking(2)
+        res = {}
+        for rows, order in tilings:
+            s.set_tiling(rows, order)
+            s.step(warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.step(steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            res["%d:%d" % (rows, order)] = e0.elapsed_time(e1) / steps * 2
+        s.check_finite()
+        s.close()
+        out["fp%d" % prec] = {"ms_per_launch": res}
+    return out
 
 
 def parse():
@@ -74,6 +112,8 @@ def parse():
     p.add_argument("--no-copy", action="store_true")
     p.add_argument("--no-fp32-long", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--tiling-sweep", action="store_true",
+                   help="time the largest workload at fixed two-step tilings instead of the benchmark (profiling aid)")
     return p.parse_args()
 
 
@@ -676,6 +716,11 @@ def main():
     from paper_0909_4039_amd import workloads
     W = workloads.LARGE
     pts = W.nr * W.nth
+    if args.tiling_sweep:
+        # the copy kernel runs too: it calibrates the HBM counters of a profiled sweep
+        print(json.dumps({"tiling_sweep": tiling_sweep(W, args.steps, args.warmup), "workload": W.name,
+                          "hbm_copy": copy_bandwidth()}), flush=True)
+        return
     # the oracle's CPU baselines run first, before anything touches the GPU
     cpu = None
     if not args.no_cpu_baseline:
@@ -688,6 +733,7 @@ def main():
     ms_step = ms / args.steps
     ups = pts * args.steps / (ms * 1e-3)
     launch_s = ms_step * kb * 1e-3               # average duration of one launch (kb steps)
+    traffic64 = measured_traffic(64, tiling[0], tiling[1]) if kb == 2 else None
     achieved = BYTES_PER_UPDATE[64] * pts / launch_s
     out = {
         "metric": "grid-point updates/s FP64/FP32 + % HBM roofline; batched vs per-mode; adjoint/fwd",
@@ -710,8 +756,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK,
                      # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE), or None
-                     "traffic": (lambda t: t["bytes_per_launch"] if t else None)(measured_traffic(64)),
-                     "traffic_detail": measured_traffic(64),
+                     "traffic": (lambda t: t["bytes_per_launch"] if t else None)(traffic64),
+                     "traffic_detail": traffic64,
                      "kernel": ("lw_step_split_kernel<double, double>" if (kb == 2 and tiling[1] == 2)
                                 else f"lw_step_kernel<double, double, {kb}>"),
                      "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
@@ -727,14 +773,15 @@ def main():
         "frac": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / HBM_PEAK,
         "note": "one step per launch: slower per step than the two-step launch above, which is what runs"}
     if not args.no_fp32:
-        ms32, _, kb32, _ = time_solver(W, 32, args.steps, args.warmup)
+        ms32, _, kb32, tiling32 = time_solver(W, 32, args.steps, args.warmup)
         ups32 = pts * args.steps / (ms32 * 1e-3)
         l32 = ms32 / args.steps * kb32 * 1e-3
         out["fp32"] = {"value": ups32, "unit": "grid-point updates/s", "ms_per_step": ms32 / args.steps,
                        "steps_per_launch": kb32,
                        "hbm_frac_per_launch": BYTES_PER_UPDATE[32] * pts / l32 / HBM_PEAK,
                        "effective_frac": BYTES_PER_UPDATE[32] * ups32 / HBM_PEAK,
-                       "traffic": measured_traffic(32),
+                       "rows_per_wave": tiling32[0], "launch_form": tiling32[1],
+                       "traffic": measured_traffic(32, tiling32[0], tiling32[1]) if kb32 == 2 else None,
                        "error_vs_fp64": fp32_error()}
         if not args.no_fp32_long:
             out["fp32"]["error_vs_fp64_full_length"] = fp32_error_full_length()
