@@ -677,6 +677,40 @@ def cpu_full_run_small():
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def cpu_windows(steps=200):
+    """The oracle (all host cores) on 200-step windows of the other workloads'
+    full grids: the 8192 x 256 source grid (zero data), the adjoint
+    workload's 4096 x 256 grid (pulse and source), and the smallest and the
+    largest instance of the 32-mode batch."""
+    import time
+    import numpy as np
+    import oracle
+    from paper_0909_4039_amd import inputs, workloads
+    oracle.build()
+    batch = workloads.batched_instances(3)
+    by_size = sorted(batch, key=lambda w: w.nr * w.nth)
+    out = {}
+    for W in (workloads.KERR_SOURCE, workloads.ADJOINT, by_size[0], by_size[-1]):
+        dt = oracle.stable_dt(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, W.steps)
+        o = oracle.Oracle(W.nr, W.nth, W.rstar_min, W.rstar_max, W.a, W.M, W.m, W.s, dt, r0=W.r0, amp=W.amp,
+                          rstar_obs=W.rstar_obs)
+        if W.pulse:
+            amp = W.pulse.get("amplitude") or inputs.seeded_amplitude(W.pulse["seed"])
+            phi, pi = inputs.pulse(W.nr, W.nth, W.rstar_min, W.rstar_max, W.m, W.pulse["center"], W.pulse["width"],
+                                   amp)
+        else:
+            phi = np.zeros((W.nth, W.nr), complex)
+            pi = np.zeros((W.nth, W.nr), complex)
+        phi, pi, _ = o.run(phi, pi, 2, record=False)   # thread start-up and page faults
+        t = time.perf_counter()
+        o.run(phi, pi, steps, 2 * dt, record=False)
+        el = time.perf_counter() - t
+        out[W.name] = {"grid": [W.nr, W.nth], "steps": steps, "seconds": el,
+                       "updates_per_s": W.nr * W.nth * steps / el}
+    out["threads"] = oracle.threads()
+    return out
+
+
 def cpu_baseline(W, seconds):
     import numpy as np
     import oracle
@@ -728,6 +762,7 @@ def main():
         cpu["host"] = cpu_model()
         cpu["single_thread"] = cpu_baseline_single_thread(args.cpu_seconds / 2)
         cpu["full_run"] = cpu_full_run_small()
+        cpu["windows"] = cpu_windows()
     import torch
     ms, dt, kb, tiling = time_solver(W, 64, args.steps, args.warmup)
     ms_step = ms / args.steps
