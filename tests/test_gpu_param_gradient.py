@@ -54,6 +54,27 @@ def test_param_gradient_against_oracle_differences(oracle_mod, param, h):
     assert got == pytest.approx(ref, rel=1e-7)
 
 
+@pytest.mark.parametrize("nr,nth,rows", [(61, 4, 2), (190, 7, 4), (47, 33, 64)])
+def test_param_gradient_ragged_grids(oracle_mod, nr, nth, rows):
+    """The fused contraction on grids of one or a few partial strips and
+    chunks (a ragged last strip, a chunk taller than the grid, a single theta
+    chunk row count), against the oracle's central differences."""
+    c = dict(CASE, nr=nr, nth=nth, rmin=-20.0, rmax=40.0, robs=13.0)
+    dt = _dt(oracle_mod, c)
+    n = 12
+    G, phi0, pi0 = _inputs(c, n, 121)
+    s = _solver(c, dt)
+    s.set_tiling(rows)
+    print(f"[gpu] param gradient a on {nr}x{nth}, {rows} rows", flush=True)
+    got = s.param_gradient("a", G, n, c["robs"], phi0, pi0, h=1e-5, checkpoint_interval=5)
+    s.close()
+    ref = oracle_mod.param_gradient_fd(c["nr"], c["nth"], c["rmin"], c["rmax"], c["a"], c["M"], c["m"], c["s"], dt,
+                                       c["r0"], c["amp"], c["robs"], "a", 1e-5, G, n, phi0, pi0)
+    print(f"[gpu] gpu {got:.12e} oracle {ref:.12e}", flush=True)
+    assert abs(ref) > 0
+    assert got == pytest.approx(ref, rel=1e-6)
+
+
 def test_source_parameters_match_the_exact_sweep(oracle_mod):
     c = CASE
     dt = _dt(oracle_mod, c)
