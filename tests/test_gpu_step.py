@@ -90,15 +90,19 @@ def test_parity_random_data(oracle_mod, case, kb):
     assert not np.any(gp[:, 0]) and not np.any(gp[:, -1])
 
 
-def test_tiling_bitwise_invariant(oracle_mod):
+@pytest.mark.parametrize("prec", [64, 32])
+def test_tiling_bitwise_invariant(oracle_mod, prec):
+    # FP32 two-step launches on one wavefront carry each point's coefficients
+    # from the first step to the second through a ring unrolled four times:
+    # 20 steps at these chunk heights end the row loop at every phase of it
     case = dict(SMALL[4])
     case["dt"] = _dt(oracle_mod, case)
-    print("[gpu] tiling invariance", flush=True)
+    print(f"[gpu] tiling invariance fp{prec}", flush=True)
     phi, pi = inputs.random_state(case["nr"], case["nth"], seed=3)
     for kb in (1, 2):
-        ref = run_gpu(case, phi, pi, 20, rows=1, kb=kb)
+        ref = run_gpu(case, phi, pi, 20, prec=prec, rows=1, kb=kb)
         for rows, order in ((2, 0), (3, 1), (7, 0), (16, 1), (64, 0), (4096, 1), (1, 2), (5, 2), (64, 2), (4096, 2)):
-            got = run_gpu(case, phi, pi, 20, rows=rows, order=order, kb=kb)
+            got = run_gpu(case, phi, pi, 20, prec=prec, rows=rows, order=order, kb=kb)
             for x, y in zip(got, ref):
                 assert np.array_equal(x, y), (rows, order, kb)
 
