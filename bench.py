@@ -794,7 +794,8 @@ def main():
                      "traffic": (lambda t: t["bytes_per_launch"] if t else None)(traffic64),
                      "traffic_detail": traffic64,
                      "kernel": ("lw_step_split_kernel<double, double>" if (kb == 2 and tiling[1] == 2)
-                                else f"lw_step_kernel<double, double, {kb}>"),
+                                else f"lw_step_kernel<double, double, {kb}, "
+                                     f"{'true' if (kb == 2 and 64 * pts > 256 * 2 ** 20) else 'false'}>"),
                      "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
         # update rate expressed as the bandwidth an unblocked step would need
         "effective": {"update_bandwidth_GBs": BYTES_PER_UPDATE[64] * ups / 1e9,
@@ -803,7 +804,7 @@ def main():
     # the kernel without temporal blocking, for comparison: one step per launch
     ms1, rows1 = time_single_step(W, 64)
     out["roofline"]["single_step_kernel"] = {
-        "kernel": "lw_step_kernel<double, double, 1>", "rows_per_wave": rows1, "launch_ms": ms1,
+        "kernel": "lw_step_kernel<double, double, 1, false>", "rows_per_wave": rows1, "launch_ms": ms1,
         "achieved": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / 1e9,
         "frac": BYTES_PER_UPDATE[64] * pts / (ms1 * 1e-3) / HBM_PEAK,
         "note": "one step per launch: slower per step than the two-step launch above, which is what runs"}

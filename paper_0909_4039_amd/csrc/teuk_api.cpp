@@ -85,6 +85,14 @@ int fail(teuk_ctx* c, int code, const char* fmt, ...) {
 // and TEUK_FP32S), FP32 for TEUK_FP32.
 size_t elem_size(int prec) { return prec == TEUK_FP32 ? sizeof(float) : sizeof(double); }
 
+// Element size of the state and the waveform: FP32 for TEUK_FP32 and
+// TEUK_FP32S, FP64 for TEUK_FP64.
+size_t storage_size(int prec) { return prec == TEUK_FP64 ? sizeof(double) : sizeof(float); }
+
+// The device's last-level cache (MI355X Infinity Cache, 256 MiB): a state
+// pair larger than this does not stay resident from one launch to the next.
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+
 // Turn a watchdog finding that has reached the host into the sticky
 // TEUK_EUNSTABLE (no wait: a scan still in flight is seen by a later call).
 int watch_poll(teuk_ctx* c) {
@@ -127,6 +135,11 @@ StepArgs<R> step_args(const teuk_ctx* c) {
     a.n_chunks = (int)((g.nth + c->rows - 1) / c->rows);
     a.order = c->order == 2 ? 0 : c->order;
     a.split = c->order == 2 ? 1 : 0;   // two fused steps on a pair of wavefronts
+    // Output rows of a streamed state are not read again within the launch:
+    // non-temporal stores measured 2-5 % faster on 32768 x 1024 FP64 and up
+    // to 3 % slower on 8192 x 256, whose state pair stays cache-resident.
+    const double state_bytes = 2.0 * double(g.nr) * double(g.nth) * 2.0 * double(storage_size(c->prec));
+    a.stream_out = state_bytes > kLastLevelCacheBytes ? 1 : 0;
     a.dt = (R)c->dt;
     a.hdt = (R)(0.5 * c->dt);
     a.inv_dr = (R)(1.0 / g.dr);

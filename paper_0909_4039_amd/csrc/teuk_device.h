@@ -88,6 +88,17 @@ __device__ __forceinline__ void st_row(R* __restrict__ base, int64_t row_elem, u
     *reinterpret_cast<typename vec2<R>::T*>(p) = w;
 }
 
+// The same store, non-temporal: the line is not kept in the caches.
+template <typename R>
+__device__ __forceinline__ void st_row_nt(R* __restrict__ base, int64_t row_elem, unsigned boff, cx<R> v) {
+    char* p = reinterpret_cast<char*>(base + 2 * row_elem) + boff;
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+
 // Row load through a pointer hidden from the optimiser (kept in the global
 // address space): its value cannot be rematerialised as a second load
 // later (which would miss in L2 and double the HBM reads), so carried rows

@@ -99,6 +99,8 @@ struct StepArgs {
     int32_t order;     // block order: 0 chunk-major, 1 strip-group-major
     int32_t kb;        // steps in this launch (1 or 2)
     int32_t split;     // kb = 2 on a pair of wavefronts, one step each (lw_step_split_kernel)
+    int32_t stream_out;  // 1: the state pair exceeds the last-level cache (FP64 two-step launches then store
+                         //    their output rows non-temporally)
     R dt, hdt, inv_dr;
     R m2ma;            // -2 m a  (Sigma^2 Im c_r = m2ma w2)
     // per fused step k: e^{-i m Omega t^{n+k}} and e^{-i m Omega (t^{n+k} + dt/2)}

@@ -247,7 +247,7 @@ __device__ __forceinline__ void pipe_iter(Pipe<R>& st, const Consts<R>& K, int k
 // u^{n+k+1} and consumes row X of stage k-1's output once both its Phi
 // (finished one iteration earlier) and its Pi are final, two rows behind.
 // S is the storage type of the state and the waveform, R the arithmetic's.
-template <typename S, typename R, int KB, bool EDGE, typename P>
+template <typename S, typename R, int KB, bool EDGE, bool NT, typename P>
 __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __restrict__ pi,
                                       S* __restrict__ phi_out, S* __restrict__ pi_out, S* __restrict__ wave,
                                       const P& A, const Consts<R>& K, int j0, int jend, unsigned boff,
@@ -316,8 +316,13 @@ __device__ __forceinline__ void march(const S* __restrict__ phi, const S* __rest
                 pipe_iter<EDGE, false, 2>(st[k], K, k, Lk, p, q, p, q, ph0, ph1, wave, rec ? A.wave_row(k) : -1, wl,
                                           j0, jend, A.alpha(), oP, okP, oQ, okQ, &rg.h, &rg.i);
             if (k == KB - 1) {
-                if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, cvt<S>(oQ));
-                if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, cvt<S>(oP));
+                if constexpr (NT) {
+                    if (okQ && out_lane) st_row_nt(pi_out, (int64_t)(Lk - 2) * nr, soff, cvt<S>(oQ));
+                    if (okP && out_lane) st_row_nt(phi_out, (int64_t)(Lk - 1) * nr, soff, cvt<S>(oP));
+                } else {
+                    if (okQ && out_lane) st_row(pi_out, (int64_t)(Lk - 2) * nr, soff, cvt<S>(oQ));
+                    if (okP && out_lane) st_row(phi_out, (int64_t)(Lk - 1) * nr, soff, cvt<S>(oP));
+                }
             } else {
                 // next stage's input row Lk-2: Phi finished one iteration ago,
                 // Pi finished now
@@ -415,7 +420,7 @@ __device__ __forceinline__ Consts<R> tile_consts(const R* __restrict__ ang, cons
 // rows per side for each extra stage.  `lds` is this wavefront's own slice
 // (no barrier).  S: storage type of the state; R: arithmetic type (FP32
 // storage with FP64 arithmetic converts on load and store).
-template <typename S, typename R, int KB, typename P>
+template <typename S, typename R, int KB, bool NT = false, typename P>
 __device__ __forceinline__ void step_tile(const S* __restrict__ phi, const S* __restrict__ pi,
                                           S* __restrict__ phi_out, S* __restrict__ pi_out,
                                           const R* __restrict__ rad_i, const R* __restrict__ rad_h,
@@ -441,9 +446,9 @@ __device__ __forceinline__ void step_tile(const S* __restrict__ phi, const S* __
     // general code; all others skip the boundary factor and the source term.
     const bool edge = __ballot(K.keep == R(0) || src_here) != 0;
     if (edge)
-        march<S, R, KB, true>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
+        march<S, R, KB, true, NT>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
     else
-        march<S, R, KB, false>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
+        march<S, R, KB, false, NT>(phi, pi, phi_out, pi_out, wave, A, K, j0, jend, boff, soff, out_lane, rec, wl);
 }
 
 // Per-tile constants of the single-mode kernel: its kernel argument (the
@@ -474,7 +479,7 @@ struct ArgParams {
 // the same theta chunk per workgroup.  S: storage type of the state and the
 // waveform; R: arithmetic type.  The FP64 body fits 3 waves per SIMD (168
 // VGPRs); the hint keeps the allocator there.
-template <typename S, typename R, int KB>
+template <typename S, typename R, int KB, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void lw_step_kernel(
     const S* __restrict__ phi, const S* __restrict__ pi, S* __restrict__ phi_out, S* __restrict__ pi_out,
     const R* __restrict__ rad_i, const R* __restrict__ rad_h, const R* __restrict__ ang, S* __restrict__ wave,
@@ -504,7 +509,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
     if (strip >= A.n_strips) return;  // wave-uniform; the kernel has no barriers
     __shared__ FwdLds<R, KB> lds_all[WG_WAVES];   // one slice per wavefront
     const ArgParams<R> P{A};
-    step_tile<S, R, KB>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, &lds_all[wid]);
+    step_tile<S, R, KB, NT>(phi, pi, phi_out, pi_out, rad_i, rad_h, ang, wave, P, strip, chunk, &lds_all[wid]);
 }
 
 
@@ -692,12 +697,22 @@ static void launch_step(const StepArgs<R>& a, hipStream_t s) {
     if (a.kb == 2 && a.split)
         hipLaunchKernelGGL((lw_step_split_kernel<S, R>), dim3(a.n_strips * a.n_chunks), dim3(2 * WAVE), 0, s, phi, pi,
                            phi_out, pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
-    else if (a.kb == 2)
-        hipLaunchKernelGGL((lw_step_kernel<S, R, 2>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, phi_out,
-                           pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
-    else
-        hipLaunchKernelGGL((lw_step_kernel<S, R, 1>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, phi_out,
-                           pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
+    else if (a.kb == 2) {
+        // FP64 states too large to stay in the last-level cache: the build
+        // with non-temporal output stores (FP32 gained nothing from it)
+        if constexpr (std::is_same<S, double>::value && std::is_same<R, double>::value) {
+            if (a.stream_out) {
+                hipLaunchKernelGGL((lw_step_kernel<S, R, 2, true>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi,
+                                   pi, phi_out, pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((lw_step_kernel<S, R, 2, false>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi,
+                           phi_out, pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
+    } else {
+        hipLaunchKernelGGL((lw_step_kernel<S, R, 1, false>), dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi,
+                           phi_out, pi_out, a.rad_i, a.rad_h, a.ang, wave, a);
+    }
 }
 void launch_step_fp64(const StepArgs<double>& a, hipStream_t s) { launch_step<double>(a, s); }
 void launch_step_fp32(const StepArgs<float>& a, hipStream_t s) { launch_step<float>(a, s); }
