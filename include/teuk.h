@@ -133,6 +133,17 @@ int teuk_extract(teuk_ctx* ctx, double rstar_obs, void* out);
 int teuk_get_time(teuk_ctx* ctx, double* t, int64_t* step);
 int teuk_set_time(teuk_ctx* ctx, double t, int64_t step);
 
+/* The clock behind those times: the base (t0 at step step0) and the
+ * current step.  teuk_set_time(t, step) is teuk_set_clock(t, step, step);
+ * it rebases the clock, so the times of the steps after it round
+ * differently from those of a run that kept its base.  A run resumed with
+ * another run's three clock values forms the same step times (and so the
+ * same source phases) bit for bit.  Any output pointer may be NULL;
+ * teuk_set_clock moves the observer's rows and the orbit table as
+ * teuk_set_time does, and fails with TEUK_EINVAL for a non-finite t0. */
+int teuk_get_clock(teuk_ctx* ctx, double* t0, int64_t* step0, int64_t* step);
+int teuk_set_clock(teuk_ctx* ctx, double t0, int64_t step0, int64_t step);
+
 /* 0: the latest state is in (phi, pi); 1: in (phi_next, pi_next);
  * negative: error code. */
 int teuk_current(teuk_ctx* ctx);

@@ -47,6 +47,8 @@ _SIGS = {
     "teuk_extract": (ctypes.c_int, [_P, _D, _P]),
     "teuk_get_time": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "teuk_set_time": (ctypes.c_int, [_P, _D, _I64]),
+    "teuk_get_clock": (ctypes.c_int, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "teuk_set_clock": (ctypes.c_int, [_P, _D, _I64, _I64]),
     "teuk_current": (ctypes.c_int, [_P]),
     "teuk_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),
     "teuk_get_tiling": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),

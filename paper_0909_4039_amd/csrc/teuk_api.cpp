@@ -712,10 +712,20 @@ int teuk_get_time(teuk_ctx* c, double* t, int64_t* step) {
     return TEUK_OK;
 }
 
-int teuk_set_time(teuk_ctx* c, double t, int64_t step) {
-    if (!c || !std::isfinite(t)) return TEUK_EINVAL;
-    c->t0 = t;
-    c->step0 = step;
+int teuk_set_time(teuk_ctx* c, double t, int64_t step) { return teuk_set_clock(c, t, step, step); }
+
+int teuk_get_clock(teuk_ctx* c, double* t0, int64_t* step0, int64_t* step) {
+    if (!c) return TEUK_EINVAL;
+    if (t0) *t0 = c->t0;
+    if (step0) *step0 = c->step0;
+    if (step) *step = c->step;
+    return TEUK_OK;
+}
+
+int teuk_set_clock(teuk_ctx* c, double t0, int64_t step0, int64_t step) {
+    if (!c || !std::isfinite(t0)) return TEUK_EINVAL;
+    c->t0 = t0;
+    c->step0 = step0;
     // the observer rows and the orbit table stay attached to the same steps
     c->obs_step0 += step - c->step;
     c->traj_step0 += step - c->step;

@@ -83,13 +83,15 @@ class Solver:
     def state_dict(self):
         """A checkpoint from which a fresh Solver of the same grid, mode, dt and
         precision continues this run bit for bit: host copies of the current
-        state, the time and step count, the source, and the part of the orbit
-        table not used yet.  Tensors and plain Python values only, so
-        ``torch.save`` / ``torch.load(weights_only=True)`` round-trip it."""
+        state, the time, the clock (see get_clock) and step count, the source,
+        and the part of the orbit table not used yet.  Tensors and plain
+        Python values only, so ``torch.save`` / ``torch.load(weights_only=True)``
+        round-trip it."""
         self.stream.synchronize()
         t, step = self.get_time()
+        t0, step0, _ = self.get_clock()
         d = {"params": dict(self.params, prec=self.prec), "phi": self.phi.cpu(), "pi": self.pi.cpu(),
-             "t": t, "step": step, "source": self.source, "trajectory": None}
+             "t": t, "step": step, "t0": t0, "step0": step0, "source": self.source, "trajectory": None}
         if self.trajectory is not None:
             used = 2 * (step - self._traj_step0)   # entries consumed by the steps taken since the table was set
             if used < 0:
@@ -104,7 +106,9 @@ class Solver:
         if {k: d["params"].get(k) for k in mine} != mine:
             raise ValueError(f"checkpoint of {d['params']} does not match this solver {mine}")
         self.set_state(d["phi"], d["pi"])
-        self.set_time(d["t"], d["step"])
+        # the clock's base, not the current time: the steps that follow form
+        # their times (and the source's phases) as the saved run would have
+        self.set_clock(d["t0"], d["step0"], d["step"])
         if d["source"] is not None:
             self.set_source(*d["source"])
         self.set_trajectory(None if d["trajectory"] is None else d["trajectory"].numpy())
@@ -162,6 +166,23 @@ class Solver:
         same amount."""
         old = self.get_time()[1]
         check(_lib.lib().teuk_set_time(self._ctx, float(t), int(step)), self._ctx)
+        if self.trajectory is not None:
+            self._traj_step0 += int(step) - old
+
+    def get_clock(self):
+        """(t0, step0, step): the time base (t0 at step step0) from which step
+        k's time is t0 + (k - step0) dt, and the current step."""
+        t0 = ctypes.c_double()
+        n0 = ctypes.c_int64()
+        n = ctypes.c_int64()
+        check(_lib.lib().teuk_get_clock(self._ctx, ctypes.byref(t0), ctypes.byref(n0), ctypes.byref(n)), self._ctx)
+        return t0.value, n0.value, n.value
+
+    def set_clock(self, t0, step0, step):
+        """Set the time base and the current step (see get_clock); the orbit
+        table moves with the current step as in set_time."""
+        old = self.get_time()[1]
+        check(_lib.lib().teuk_set_clock(self._ctx, float(t0), int(step0), int(step)), self._ctx)
         if self.trajectory is not None:
             self._traj_step0 += int(step) - old
 

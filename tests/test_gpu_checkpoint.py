@@ -1,5 +1,5 @@
 """Checkpoint and resume: Solver.state_dict / load_state_dict around
-teuk_get_time / teuk_set_time and teuk_set_trajectory.  A run of 2n steps
+teuk_get_clock / teuk_set_clock and teuk_set_trajectory.  A run of 2n steps
 equals n steps, a checkpoint written with torch.save and read back with
 torch.load(weights_only=True) into a fresh solver, and n more steps, bit for
 bit, for a fixed orbit and for an inspiral.
@@ -37,7 +37,7 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral, prec):
     a.set_observer(60.0, n + 1)
     a.step(n)
     torch.cuda.synchronize()
-    want = (a.phi.cpu().numpy(), a.pi.cpu().numpy(), a.wave.cpu().numpy(), a.get_time())
+    want = (a.phi.cpu().numpy(), a.pi.cpu().numpy(), a.wave.cpu().numpy(), a.get_time(), a.get_clock())
     a.close()
 
     b = make(dt, prec)
@@ -45,10 +45,14 @@ def test_resume_from_a_saved_checkpoint_is_bitwise(tmp_path, inspiral, prec):
     b.set_observer(60.0, n + 1)
     b.step(n)
     torch.cuda.synchronize()
-    got = (b.phi.cpu().numpy(), b.pi.cpu().numpy(), b.wave.cpu().numpy(), b.get_time())
+    got = (b.phi.cpu().numpy(), b.pi.cpu().numpy(), b.wave.cpu().numpy(), b.get_time(), b.get_clock())
     for x, y in zip(want[:3], got[:3]):
         assert np.array_equal(x, y)
     assert got[3] == want[3]
+    # the resumed run keeps the saved run's time base (rebasing it at the
+    # checkpoint would round the later step times, so the source's phases,
+    # differently)
+    assert got[4] == want[4]
     # a checkpoint of another run does not load
     c = make(dt, 96 - prec)                       # the other precision
     with pytest.raises(ValueError):
