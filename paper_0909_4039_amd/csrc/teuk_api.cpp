@@ -1029,10 +1029,12 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
 // step per launch) from (ip, iq) into (op, oq) at time t, with a
 // fixed-orbit source; no waveform is recorded.
 static StepArgs<double> step_args_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq,
-                                     double t) {
+                                     double t, int rows) {
     const Geometry& g = x->geo;
     StepArgs<double> a = step_args<double>(x);
     a.kb = 1;
+    a.rows = rows;
+    a.n_chunks = (int)((g.nth + rows - 1) / rows);
     const int so = WAVE - 2;
     a.n_strips = (int)((g.nr + so - 1) / so);
     a.n_tiles = a.n_strips * a.n_chunks;
@@ -1052,12 +1054,43 @@ static StepArgs<double> step_args_at(teuk_ctx* x, const double* ip, const double
     return a;
 }
 
-// One FP64 step of x from (ip, iq) into (op, oq) at time t (see
-// step_args_at); leaves x's bound state, step count and time alone.
-static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t) {
-    launch_step_fp64(step_args_at(x, ip, iq, op, oq, t), x->stream);
+// One FP64 step of x from (ip, iq) into (op, oq) at time t, `rows` theta
+// rows per wave (see step_args_at); leaves x's bound state, step count and
+// time alone.
+static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t, int rows) {
+    launch_step_fp64(step_args_at(x, ip, iq, op, oq, t, rows), x->stream);
     HIP_TRY(x, hipGetLastError());
     return TEUK_OK;
+}
+
+// Theta rows per wave of the parameter sweep's one-step launches (the
+// recomputed forward steps and the fused contraction, 4 wavefronts per
+// workgroup).  The context's rows are tuned for its own launches, often two
+// fused steps on tall chunks, which leave a one-step launch of a mid-size
+// grid short of workgroups.  A launch takes ceil(blocks / resident) rounds
+// of workgroups, each about as long as its chunk plus 2 halo rows, and the
+// contraction does two steps' work per point: the height r from 1 to 16
+// (the one-step default) that minimises (2 rounds_pdot + rounds_step)(r + 2)
+// is taken, the tallest on a tie.  It depends on the grid and the device
+// only, so results repeat bit for bit.  On 4096 x 256 (256 CUs, 2 and 3
+// resident workgroups per CU) the model ranks 9 and 10 rows first; 10 rows
+// measured 1.80 s for the sweep against 1.88 s at 6, 2.00 s at 8 and
+// 2.12 s at 16.
+static int sweep_rows(const Geometry& g, int cus, int pdot_per_cu, int step_per_cu) {
+    const int64_t groups = ((g.nr + WAVE - 3) / (WAVE - 2) + WG_WAVES - 1) / WG_WAVES;   // strip groups
+    const int64_t cap_p = (int64_t)pdot_per_cu * cus, cap_s = (int64_t)step_per_cu * cus;
+    const int top = (int)std::min<int64_t>(16, g.nth);
+    int best = 1;
+    int64_t best_cost = -1;
+    for (int r = 1; r <= top; ++r) {
+        const int64_t blocks = groups * ((g.nth + r - 1) / r);
+        const int64_t cost = (2 * ((blocks + cap_p - 1) / cap_p) + (blocks + cap_s - 1) / cap_s) * (r + 2);
+        if (best_cost < 0 || cost <= best_cost) {
+            best_cost = cost;
+            best = r;
+        }
+    }
+    return best;
 }
 
 // Workspace of a parameter gradient: two adjoint pairs, the reverse step's
@@ -1094,7 +1127,7 @@ static int64_t default_interval(int64_t n) {
 // step_{p+h}(u^k) - step_{p-h}(u^k) (one fused launch, lw_pdot_kernel, that
 // does not store the two steps) and take the reverse step to lambda^k.
 static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double alpha, const double* g, int64_t n,
-                       double t_start, const double* phi0, const double* pi0, int64_t C, char* ws,
+                       double t_start, const double* phi0, const double* pi0, int64_t C, int rows, char* ws,
                        std::vector<double>& res, const double** lam0) {
     const Geometry& geo = c->geo;
     const ParamLayout L = param_layout(c, n, C);
@@ -1117,7 +1150,7 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
     double* cur = ckpt(0);
     for (int64_t k = 0; k + 1 < n; ++k) {   // u^n itself is not needed
         double* next = ((k + 1) % C == 0) ? ckpt((k + 1) / C) : (cur == tmp[0] ? tmp[1] : tmp[0]);
-        int rc = step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt);
+        int rc = step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt, rows);
         if (rc != TEUK_OK) return rc;
         cur = next;
     }
@@ -1133,15 +1166,15 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
         for (int64_t i = 1; i < k1 - k0; ++i) {
             double* in = seg(j, i - 1);
             double* out = seg(j, i);
-            int rc = step_at(c, in, pi_of(in), out, pi_of(out), t_start + double(k0 + i - 1) * dt);
+            int rc = step_at(c, in, pi_of(in), out, pi_of(out), t_start + double(k0 + i - 1) * dt, rows);
             if (rc != TEUK_OK) return rc;
         }
         for (int64_t k = k1 - 1; k >= k0; --k) {
             double* u = seg(j, k - k0);
             const double t = t_start + double(k) * dt;
             PdotArgs pd;
-            pd.s[0] = step_args_at(xp, u, pi_of(u), nullptr, nullptr, t);
-            pd.s[1] = step_args_at(xm, u, pi_of(u), nullptr, nullptr, t);
+            pd.s[0] = step_args_at(xp, u, pi_of(u), nullptr, nullptr, t, rows);
+            pd.s[1] = step_args_at(xm, u, pi_of(u), nullptr, nullptr, t, rows);
             pd.lp = lam[li];
             pd.lq = pi_of(lam[li]);
             pd.part = parts;
@@ -1203,6 +1236,12 @@ static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double
     double alpha;
     if (!observer_index(geo, rstar_obs, iobs, alpha))
         return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+        return fail(c, TEUK_EDEVICE, "compute unit count unavailable");
+    int pdot_per_cu = 1, step_per_cu = 1;
+    sweep_blocks_per_cu(&pdot_per_cu, &step_per_cu);
+    const int rows = sweep_rows(geo, cus, pdot_per_cu, step_per_cu);
     // the two perturbed contexts: same grid, mode, dt, tiling and source, one parameter moved by +-h
     teuk_grid gr{geo.nr, geo.nth, geo.rmin, geo.rmax};
     double pa[2] = {geo.a, geo.a}, pM[2] = {geo.M, geo.M}, pr0[2] = {c->r0, c->r0}, pamp[2] = {c->amp, c->amp};
@@ -1232,7 +1271,7 @@ static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double
             rc = fail(c, TEUK_EDEVICE, "perturbed context: %s", x[i]->err);
             break;
         }
-        x[i]->rows = c->rows;
+        x[i]->rows = rows;
         if (c->has_src) {
             rc = teuk_set_source_impl(x[i], pr0[i], pamp[i], c->sig_r, c->sig_th);
             if (rc != TEUK_OK) rc = fail(c, rc, "perturbed source: %s", x[i]->err);
@@ -1242,7 +1281,7 @@ static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double
     const double* lam0 = nullptr;
     if (rc == TEUK_OK)
         rc = param_sweep(c, x[0], x[1], iobs, alpha, (const double*)dL_dwave, n_steps, t_start, (const double*)phi0,
-                         (const double*)pi0, C, (char*)workspace, res, &lam0);
+                         (const double*)pi0, C, rows, (char*)workspace, res, &lam0);
     if (rc != TEUK_OK) return rc;
     // sum in step order, then the central difference's 1/(2h)
     double sum = 0.0;

@@ -237,6 +237,9 @@ struct PdotArgs {
     double* part;
 };
 int64_t pdot_parts(const StepArgs<double>& a);
+// Workgroups per CU that stay resident for lw_pdot_kernel and for the
+// one-step FP64 step kernel (at least 1 each).
+void sweep_blocks_per_cu(int* pdot, int* step1);
 void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s);
 void launch_watch_fp64(const double* x, int64_t n, double lim, int64_t tag, unsigned long long* found,
                        hipStream_t s);

@@ -841,6 +841,15 @@ __global__ __launch_bounds__(256) void pdot_sum_kernel(const double* __restrict_
 
 int64_t pdot_parts(const StepArgs<double>& a) { return (int64_t)a.n_strips * a.n_chunks; }
 
+void sweep_blocks_per_cu(int* pdot, int* step1) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_pdot_kernel, WAVE * WG_WAVES, 0);
+    *pdot = (e == hipSuccess && n > 0) ? n : 1;
+    n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_step_kernel<double, double, 1, false>, WAVE * WG_WAVES, 0);
+    *step1 = (e == hipSuccess && n > 0) ? n : 1;
+}
+
 void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s) {
     const StepArgs<double>& a = b.s[0];
     const int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
