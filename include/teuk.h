@@ -252,11 +252,14 @@ int teuk_adjoint_moving(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, i
  * segment of C states from its checkpoint, and one launch per reverse step
  * evaluates both perturbed steps on the same u^k and contracts their
  * difference with lambda^{k+1} without storing either.  So memory is
- * ceil(n/C) + C + 1 states, and the cost is about five and a half forward
- * runs.  The sweep's one-step launches take their own theta rows per wave
- * (enough wavefronts for the device's compute units, at most 16), not the
- * context's tiling.  Contractions and their sum follow fixed orders
- * (results repeat bit for bit on a device).
+ * ceil(n/C) + C + 1 states (plus the contraction's per-tile parts for the
+ * C steps of a segment, summed once per segment), and the cost is about
+ * five and a half forward runs.  The sweep's one-step launches take their
+ * own theta rows per wave (enough wavefronts for the device's compute
+ * units, at most 16), not the context's tiling.  Contractions and their sum
+ * follow fixed orders (results repeat bit for bit on a device).
+ * teuk_param_gradient_workspace_bytes returns TEUK_EINVAL for negative
+ * arguments and TEUK_EDEVICE if the device cannot be queried.
  *   dL_dwave: device, (n_steps + 1) x n_theta complex128, as teuk_adjoint.
  *   phi0, pi0: device, n_theta x n_rstar complex128, the initial data (read).
  *   workspace: device, teuk_param_gradient_workspace_bytes(ctx, n_steps, C)

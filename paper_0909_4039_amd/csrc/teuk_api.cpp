@@ -1093,25 +1093,37 @@ static int sweep_rows(const Geometry& g, int cus, int pdot_per_cu, int step_per_
     return best;
 }
 
+// sweep_rows for c's grid on c's device; 0 if the device cannot be queried.
+static int sweep_rows(const teuk_ctx* c) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+        return 0;
+    int pdot_per_cu = 1, step_per_cu = 1;
+    sweep_blocks_per_cu(&pdot_per_cu, &step_per_cu);
+    return sweep_rows(c->geo, cus, pdot_per_cu, step_per_cu);
+}
+
 // Workspace of a parameter gradient: two adjoint pairs, the reverse step's
 // gradient slots, ceil(n / C) checkpoints, C - 1 segment states, the fused
-// contraction's per-tile parts (at most one per strip and theta row) and
-// one double per step.  A state is Phi and Pi, complex128 [nth][nr] each.
+// contraction's per-tile parts for each step of a segment (summed once per
+// segment) and one double per step.  A state is Phi and Pi, complex128
+// [nth][nr] each.  rows: the sweep's theta rows per wave (sweep_rows).
 struct ParamLayout {
-    int64_t state, lam, slots, ckpt, seg, parts, res, total, n_ckpt;
+    int64_t state, lam, slots, ckpt, seg, parts, n_parts, res, total, n_ckpt;
 };
-static ParamLayout param_layout(const teuk_ctx* c, int64_t n, int64_t C) {
+static ParamLayout param_layout(const teuk_ctx* c, int64_t n, int64_t C, int rows) {
     ParamLayout L;
     const int64_t npts = c->geo.nr * c->geo.nth;
     const int64_t strips1 = (c->geo.nr + WAVE - 3) / (WAVE - 2);   // strips of a one-step launch
     L.state = round256(2 * npts * 16);
     L.n_ckpt = n > 0 ? (n + C - 1) / C : 1;
+    L.n_parts = strips1 * ((c->geo.nth + rows - 1) / rows);
     L.lam = 0;
     L.slots = L.lam + 2 * L.state;
     L.ckpt = L.slots + round256(adjoint_slots_max(c->geo) * 3 * 8);
     L.seg = L.ckpt + L.n_ckpt * L.state;
     L.parts = L.seg + std::max<int64_t>(C - 1, 0) * L.state;
-    L.res = L.parts + round256(strips1 * c->geo.nth * 8);
+    L.res = L.parts + round256(std::max<int64_t>(std::min(C, n), 1) * L.n_parts * 8);
     L.total = L.res + round256(std::max<int64_t>(n, 1) * 8);
     return L;
 }
@@ -1130,7 +1142,7 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
                        double t_start, const double* phi0, const double* pi0, int64_t C, int rows, char* ws,
                        std::vector<double>& res, const double** lam0) {
     const Geometry& geo = c->geo;
-    const ParamLayout L = param_layout(c, n, C);
+    const ParamLayout L = param_layout(c, n, C, rows);
     const int64_t npts = geo.nr * geo.nth;
     auto state = [&](int64_t off) { return (double*)(ws + off); };
     auto pi_of = [&](double* phi) { return phi + 2 * npts; };
@@ -1160,6 +1172,8 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
     launch_fill_zero(slots, adjoint_slots_max(geo) * 3, c->stream);
     HIP_TRY(c, hipGetLastError());
     AdjArgs a = adjoint_args(c, g, iobs, alpha, slots);
+    if (pdot_parts(step_args_at(xp, nullptr, nullptr, nullptr, nullptr, t_start, rows)) != L.n_parts)
+        return fail(c, TEUK_EINVAL, "contraction parts do not match the workspace layout");
     int li = 0;   // lam[li] holds lambda^{k+1}
     for (int64_t j = L.n_ckpt - 1; j >= 0 && n > 0; --j) {
         const int64_t k0 = j * C, k1 = std::min(k0 + C, n);
@@ -1177,8 +1191,8 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
             pd.s[1] = step_args_at(xm, u, pi_of(u), nullptr, nullptr, t, rows);
             pd.lp = lam[li];
             pd.lq = pi_of(lam[li]);
-            pd.part = parts;
-            launch_param_pdot(pd, u, pi_of(u), dres + k, c->stream);
+            pd.part = parts + (k - k0) * L.n_parts;
+            launch_param_pdot(pd, u, pi_of(u), c->stream);
             HIP_TRY(c, hipGetLastError());
             adjoint_launch_args(c, a, 1, k + 1, t_start, true);
             a.lp = lam[li];
@@ -1189,6 +1203,9 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
             HIP_TRY(c, hipGetLastError());
             li = 1 - li;
         }
+        // the segment's contractions, one fixed-order sum per step
+        launch_pdot_sums(parts, L.n_parts, k1 - k0, dres + k0, c->stream);
+        HIP_TRY(c, hipGetLastError());
     }
     res.assign((size_t)std::max<int64_t>(n, 0), 0.0);
     if (n > 0)
@@ -1201,7 +1218,9 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
 int64_t teuk_param_gradient_workspace_bytes(teuk_ctx* c, int64_t n_steps, int64_t checkpoint_interval) {
     if (!c || n_steps < 0 || checkpoint_interval < 0) return TEUK_EINVAL;
     const int64_t C = checkpoint_interval > 0 ? checkpoint_interval : default_interval(n_steps);
-    return param_layout(c, n_steps, C).total;
+    const int rows = sweep_rows(c);
+    if (rows < 1) return TEUK_EDEVICE;
+    return param_layout(c, n_steps, C, rows).total;
 }
 
 static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double rstar_obs, const void* dL_dwave,
@@ -1220,7 +1239,9 @@ static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double
     if ((param == TEUK_PARAM_R0 || param == TEUK_PARAM_AMP) && !c->has_src)
         return fail(c, TEUK_ESTATE, "no source: teuk_set_source first");
     const int64_t C = checkpoint_interval > 0 ? checkpoint_interval : default_interval(n_steps);
-    const ParamLayout L = param_layout(c, n_steps, C);
+    const int rows = sweep_rows(c);
+    if (rows < 1) return fail(c, TEUK_EDEVICE, "compute unit count unavailable");
+    const ParamLayout L = param_layout(c, n_steps, C, rows);
     if (!dL_dwave || !workspace) return fail(c, TEUK_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % 256 != 0) return fail(c, TEUK_EINVAL, "workspace not 256-byte aligned");
     if ((uintptr_t)dL_dwave % 16 != 0) return fail(c, TEUK_EINVAL, "dL_dwave must be 16-byte aligned");
@@ -1236,12 +1257,6 @@ static int teuk_param_gradient_impl(teuk_ctx* c, int32_t param, double h, double
     double alpha;
     if (!observer_index(geo, rstar_obs, iobs, alpha))
         return fail(c, TEUK_EINVAL, "rstar_obs = %g outside the open grid interval", rstar_obs);
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
-        return fail(c, TEUK_EDEVICE, "compute unit count unavailable");
-    int pdot_per_cu = 1, step_per_cu = 1;
-    sweep_blocks_per_cu(&pdot_per_cu, &step_per_cu);
-    const int rows = sweep_rows(geo, cus, pdot_per_cu, step_per_cu);
     // the two perturbed contexts: same grid, mode, dt, tiling and source, one parameter moved by +-h
     teuk_grid gr{geo.nr, geo.nth, geo.rmin, geo.rmax};
     double pa[2] = {geo.a, geo.a}, pM[2] = {geo.M, geo.M}, pr0[2] = {c->r0, c->r0}, pamp[2] = {c->amp, c->amp};

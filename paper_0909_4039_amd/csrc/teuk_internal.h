@@ -229,7 +229,8 @@ void launch_moving_slot_sum(const double* slots, int64_t n_slots, int kb, int64_
                             hipStream_t s);
 // Fused parameter-gradient contraction (lw_pdot_kernel): s[0] and s[1] are
 // one-step launches of the contexts built at p + h and p - h on the same
-// grid and tiling; part holds pdot_parts(s[0]) doubles.
+// grid and tiling; the launch writes pdot_parts(s[0]) per-tile parts into
+// part, which launch_pdot_sums adds up later.
 struct PdotArgs {
     StepArgs<double> s[2];
     const double* lp;   // lambda^{k+1}: interleaved complex [nth][nr]
@@ -240,7 +241,10 @@ int64_t pdot_parts(const StepArgs<double>& a);
 // Workgroups per CU that stay resident for lw_pdot_kernel and for the
 // one-step FP64 step kernel (at least 1 each).
 void sweep_blocks_per_cu(int* pdot, int* step1);
-void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s);
+void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, hipStream_t s);
+// out[i] = the sum, in a fixed order, of the n_parts doubles at
+// part + i n_parts, for i < n_steps (one launch).
+void launch_pdot_sums(const double* part, int64_t n_parts, int64_t n_steps, double* out, hipStream_t s);
 void launch_watch_fp64(const double* x, int64_t n, double lim, int64_t tag, unsigned long long* found,
                        hipStream_t s);
 void launch_watch_fp32(const float* x, int64_t n, float lim, int64_t tag, unsigned long long* found,

@@ -823,11 +823,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     if (lane == 0) B.part[(int64_t)chunk * A.n_strips + strip] = acc;
 }
 
-// Sum of the tiles' parts in a fixed order into *out (one workgroup).
+// Sums of the tiles' parts in a fixed order: workgroup b adds the n parts
+// at part + b n into out[b].
 __global__ __launch_bounds__(256) void pdot_sum_kernel(const double* __restrict__ part, int64_t n,
                                                        double* __restrict__ out) {
     __shared__ double red[256];
     const int t = threadIdx.x;
+    part += (int64_t)blockIdx.x * n;
     double s = 0.0;
     for (int64_t i = t; i < n; i += 256) s += part[i];
     red[t] = s;
@@ -836,7 +838,7 @@ __global__ __launch_bounds__(256) void pdot_sum_kernel(const double* __restrict_
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) out[0] = red[0];
+    if (t == 0) out[blockIdx.x] = red[0];
 }
 
 int64_t pdot_parts(const StepArgs<double>& a) { return (int64_t)a.n_strips * a.n_chunks; }
@@ -850,11 +852,15 @@ void sweep_blocks_per_cu(int* pdot, int* step1) {
     *step1 = (e == hipSuccess && n > 0) ? n : 1;
 }
 
-void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, double* out, hipStream_t s) {
+void launch_param_pdot(const PdotArgs& b, const double* phi, const double* pi, hipStream_t s) {
     const StepArgs<double>& a = b.s[0];
     const int blocks = ((a.n_strips + WG_WAVES - 1) / WG_WAVES) * a.n_chunks;
     hipLaunchKernelGGL(lw_pdot_kernel, dim3(blocks), dim3(WAVE * WG_WAVES), 0, s, phi, pi, b);
-    hipLaunchKernelGGL(pdot_sum_kernel, dim3(1), dim3(256), 0, s, b.part, pdot_parts(a), out);
+}
+
+void launch_pdot_sums(const double* part, int64_t n_parts, int64_t n_steps, double* out, hipStream_t s) {
+    if (n_steps > 0)
+        hipLaunchKernelGGL(pdot_sum_kernel, dim3((unsigned)n_steps), dim3(256), 0, s, part, n_parts, out);
 }
 
 // Batched launches: every instance of a batch advances kb steps in one
