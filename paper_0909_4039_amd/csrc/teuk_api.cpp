@@ -1029,13 +1029,13 @@ int teuk_adjoint(teuk_ctx* c, double rstar_obs, const void* dL_dwave, int64_t n_
 // step per launch) from (ip, iq) into (op, oq) at time t, with a
 // fixed-orbit source; no waveform is recorded.
 static StepArgs<double> step_args_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq,
-                                     double t, int rows) {
+                                     double t, int rows, int kb = 1) {
     const Geometry& g = x->geo;
     StepArgs<double> a = step_args<double>(x);
-    a.kb = 1;
+    a.kb = kb;
     a.rows = rows;
     a.n_chunks = (int)((g.nth + rows - 1) / rows);
-    const int so = WAVE - 2;
+    const int so = WAVE - 2 * kb;
     a.n_strips = (int)((g.nr + so - 1) / so);
     a.n_tiles = a.n_strips * a.n_chunks;
     for (int q = 0; q < KB_MAX; ++q) {
@@ -1054,11 +1054,12 @@ static StepArgs<double> step_args_at(teuk_ctx* x, const double* ip, const double
     return a;
 }
 
-// One FP64 step of x from (ip, iq) into (op, oq) at time t, `rows` theta
-// rows per wave (see step_args_at); leaves x's bound state, step count and
-// time alone.
-static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t, int rows) {
-    launch_step_fp64(step_args_at(x, ip, iq, op, oq, t, rows), x->stream);
+// kb FP64 steps of x (one launch) from (ip, iq) into (op, oq) from time
+// t, `rows` theta rows per wave (see step_args_at; kb = 2 in the launch
+// form of x's tiling); leaves x's bound state, step count and time alone.
+static int step_at(teuk_ctx* x, const double* ip, const double* iq, double* op, double* oq, double t, int rows,
+                   int kb = 1) {
+    launch_step_fp64(step_args_at(x, ip, iq, op, oq, t, rows, kb), x->stream);
     HIP_TRY(x, hipGetLastError());
     return TEUK_OK;
 }
@@ -1157,14 +1158,20 @@ static int param_sweep(teuk_ctx* c, teuk_ctx* xp, teuk_ctx* xm, int iobs, double
     HIP_TRY(c, hipMemcpyAsync(ckpt(0), phi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(pi_of(ckpt(0)), pi0, npts * 16, hipMemcpyDeviceToDevice, c->stream));
     // forward states between checkpoints alternate between the two adjoint
-    // pairs, which are not in use yet
+    // pairs, which are not in use yet; u^n itself is not needed.  Only every
+    // C-th state is kept, so this pass takes the context's own launches, two
+    // fused steps where no checkpoint falls between them (bitwise equal to
+    // single steps).
     double* tmp[2] = {lam[0], lam[1]};
     double* cur = ckpt(0);
-    for (int64_t k = 0; k + 1 < n; ++k) {   // u^n itself is not needed
-        double* next = ((k + 1) % C == 0) ? ckpt((k + 1) / C) : (cur == tmp[0] ? tmp[1] : tmp[0]);
-        int rc = step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt, rows);
+    for (int64_t k = 0; k + 1 < n;) {
+        const int kb = (c->kblock == 2 && k + 2 < n && (k + 1) % C != 0) ? 2 : 1;
+        double* next = ((k + kb) % C == 0) ? ckpt((k + kb) / C) : (cur == tmp[0] ? tmp[1] : tmp[0]);
+        int rc = kb == 2 ? step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt, c->rows, 2)
+                         : step_at(c, cur, pi_of(cur), next, pi_of(next), t_start + double(k) * dt, rows);
         if (rc != TEUK_OK) return rc;
         cur = next;
+        k += kb;
     }
     // lambda^n = E^H g^n
     launch_adjoint_init(lam[0], pi_of(lam[0]), g + 2 * n * geo.nth, npts, (int)geo.nr, iobs, alpha, c->stream);
