@@ -56,9 +56,10 @@ def test_param_gradient_against_oracle_differences(oracle_mod, param, h):
 
 @pytest.mark.parametrize("nr,nth,rows", [(61, 4, 2), (190, 7, 4), (47, 33, 64)])
 def test_param_gradient_ragged_grids(oracle_mod, nr, nth, rows):
-    """The fused contraction on grids of one or a few partial strips and
-    chunks (a ragged last strip, a chunk taller than the grid, a single theta
-    chunk row count), against the oracle's central differences."""
+    """Grids of one or a few partial strips (a ragged last strip), with the
+    context's tiling at 2, 4 and 64 rows (a chunk taller than the grid) for
+    the checkpointing pass and the sweep's one-step launches at their own
+    height, against the oracle's central differences."""
     c = dict(CASE, nr=nr, nth=nth, rmin=-20.0, rmax=40.0, robs=13.0)
     dt = _dt(oracle_mod, c)
     n = 12
@@ -101,6 +102,25 @@ def test_checkpoint_interval_does_not_change_the_result(oracle_mod):
     # zero steps: only lambda^0 = E^H g^0, and no parameter dependence
     g0, lp, lq = s.param_gradient("a", G[:1], 0, c["robs"], phi0, pi0, h=1e-5, want_initial=True)
     assert g0 == 0.0 and np.count_nonzero(lp.cpu().numpy()) > 0 and not np.any(lq.cpu().numpy())
+    s.close()
+
+
+def test_param_gradient_does_not_depend_on_the_context_tiling(oracle_mod):
+    # the sweep's one-step launches take a chunk height of their own, and its
+    # checkpointing pass the context's launches, whose two fused steps equal
+    # single steps bit for bit: the context's tiling changes no bit
+    c = CASE
+    dt = _dt(oracle_mod, c)
+    G, phi0, pi0 = _inputs(c, N, 104)
+    s = _solver(c, dt)
+    s.set_blocking(1)
+    ref = s.param_gradient("a", G, N, c["robs"], phi0, pi0, h=1e-5, checkpoint_interval=8)
+    for rows, order, kb in ((2, 0, 1), (5, 1, 2), (16, 0, 2), (12, 2, 2), (64, 0, 2)):
+        s.set_tiling(rows, order)
+        s.set_blocking(kb)
+        print(f"[gpu] param gradient a, context tiling {rows}:{order}, {kb} steps per launch", flush=True)
+        got = s.param_gradient("a", G, N, c["robs"], phi0, pi0, h=1e-5, checkpoint_interval=8)
+        assert got == ref, (rows, order, kb)
     s.close()
 
 
