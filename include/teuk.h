@@ -254,10 +254,12 @@ int teuk_adjoint_moving(teuk_ctx* ctx, double rstar_obs, const void* dL_dwave, i
  * difference with lambda^{k+1} without storing either.  So memory is
  * ceil(n/C) + C + 1 states (plus the contraction's per-tile parts for the
  * C steps of a segment, summed once per segment), and the cost is about
- * five and a half forward runs.  The sweep's one-step launches take their
- * own theta rows per wave (enough wavefronts for the device's compute
- * units, at most 16), not the context's tiling.  Contractions and their sum
- * follow fixed orders (results repeat bit for bit on a device).
+ * five forward runs.  The forward run takes the context's own launches;
+ * the sweep's one-step launches take their own theta rows per wave (1 to
+ * 16, from the grid, the device's compute units and the workgroups they
+ * hold resident), so the context's tiling changes no bit of the result.
+ * Contractions and their sum follow fixed orders (results repeat bit for
+ * bit on a device).
  * teuk_param_gradient_workspace_bytes returns TEUK_EINVAL for negative
  * arguments and TEUK_EDEVICE if the device cannot be queried.
  *   dL_dwave: device, (n_steps + 1) x n_theta complex128, as teuk_adjoint.
