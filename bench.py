@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+TARGET_FRAC = 0.70         # per-launch fraction of HBM_PEAK the step kernel is built towards
 BYTES_PER_UPDATE = {64: 64, 32: 32}   # read (Phi, Pi) + write (Phi', Pi'), complex
 KERNEL_SRCS = [os.path.join(ROOT, "paper_0909_4039_amd", "csrc", f) for f in ("teuk_kernels.hip", "teuk_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_traffic.json")
@@ -796,10 +797,13 @@ def main():
                      "kernel": ("lw_step_split_kernel<double, double>" if (kb == 2 and tiling[1] == 2)
                                 else f"lw_step_kernel<double, double, {kb}, "
                                      f"{'true' if (kb == 2 and 64 * pts > 256 * 2 ** 20) else 'false'}>"),
-                     "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3},
+                     "bytes_per_launch": BYTES_PER_UPDATE[64] * pts, "launch_ms": launch_s * 1e3,
+                     "target_frac": TARGET_FRAC, "gap_to_target": TARGET_FRAC - achieved / HBM_PEAK},
         # update rate expressed as the bandwidth an unblocked step would need
         "effective": {"update_bandwidth_GBs": BYTES_PER_UPDATE[64] * ups / 1e9,
-                      "frac_of_hbm_peak": BYTES_PER_UPDATE[64] * ups / HBM_PEAK},
+                      "frac_of_hbm_peak": BYTES_PER_UPDATE[64] * ups / HBM_PEAK,
+                      "note": "not a roofline figure: two fused steps move the bytes of one, and this counts "
+                              "64 B per update; roofline.frac is the per-launch fraction"},
     }
     # the kernel without temporal blocking, for comparison: one step per launch
     ms1, rows1 = time_single_step(W, 64)
