@@ -65,10 +65,13 @@ def measured_traffic(prec, rows, order):
 
 
 # Two-step tilings (theta rows per wave, launch form: 0 one wavefront per
-# tile, 2 a pair) that --tiling-sweep times, and whose HBM counters the
-# traffic record holds: the autotuner's usual choices on 32768 x 1024.
-SWEEP_TILINGS = {64: [(64, 0), (96, 0), (128, 0), (192, 0), (256, 0), (64, 2), (96, 2)],
-                 32: [(48, 0), (64, 0), (96, 0), (128, 0), (192, 0), (48, 2), (64, 2), (96, 2)]}
+# tile in chunk-major block order, 1 the same in group-major order, 2 a
+# pair) that --tiling-sweep times, and whose HBM counters the traffic record
+# holds: the autotuner's usual choices on 32768 x 1024.
+SWEEP_TILINGS = {64: [(64, 0), (96, 0), (128, 0), (192, 0), (256, 0), (64, 1), (96, 1), (128, 1), (192, 1),
+                      (64, 2), (96, 2)],
+                 32: [(48, 0), (64, 0), (96, 0), (128, 0), (192, 0), (48, 1), (64, 1), (96, 1), (128, 1),
+                      (48, 2), (64, 2), (96, 2)]}
 
 
 def tiling_sweep(W, steps, warmup):
@@ -788,7 +791,9 @@ def main():
                    "a": W.a, "m": W.m, "s": W.s, "r0": W.r0, "rstar_obs": W.rstar_obs, "dt": dt,
                    "initial_data": "zero, source on", "steps_per_launch": kb,
                    "rows_per_wave": tiling[0],
-                   "launch_form": "pair of wavefronts per tile" if tiling[1] == 2 else "one wavefront per tile"},
+                   "launch_form": {0: "one wavefront per tile, chunk-major blocks",
+                                   1: "one wavefront per tile, group-major blocks"}.get(tiling[1],
+                                                                                       "pair of wavefronts per tile")},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK,
                      # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE), or None
