@@ -58,7 +58,7 @@ def measured_traffic(prec, rows, order):
         return {"bytes_per_launch": e["fetch_bytes"] + e["write_bytes"], "fetch_bytes": e["fetch_bytes"],
                 "write_bytes": e["write_bytes"],
                 "source": (f"{os.path.relpath(TRAFFIC_FILE, ROOT)}: rocprofv3 counters taken on the kernel code of "
-                           f"commit {rec.get('kernel_commit', '?')} (same code hash as this build) at {rows} rows "
+                           f"commit {rec.get('kernel_commit', '?')} (the same kernel code as the library measured here) at {rows} rows "
                            f"per wave, launch form {order}; not this run's")}
     except (OSError, KeyError, ValueError):
         return None
