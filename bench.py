@@ -635,17 +635,25 @@ def fp32_error():
 
 
 def cpu_model():
-    """The host CPU's model name and logical core count, as the kernel reports them."""
-    name = None
+    """The host CPU's model name, its family / model / stepping numbers and
+    clock (which name the core generation where a virtual machine shortens
+    the name), and the logical core count, as the kernel reports them."""
+    fields = {"model name": "model", "cpu family": "family", "model": "model_number", "stepping": "stepping",
+              "cpu MHz": "mhz"}
+    out = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    name = line.split(":", 1)[1].strip()
-                    break
+                if not line.strip():
+                    break          # the first processor's block only
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key in fields:
+                    out[fields[key]] = val.strip()
     except OSError:
         pass
-    return {"model": name, "logical_cpus": os.cpu_count()}
+    return {"model": out.get("model"), "family": out.get("family"), "model_number": out.get("model_number"),
+            "stepping": out.get("stepping"), "mhz": out.get("mhz"), "logical_cpus": os.cpu_count()}
 
 
 _CPU_FULL_RUN = """
