@@ -96,6 +96,43 @@ def test_checkpoint_after_relabelling_the_step_keeps_the_orbit(tmp_path):
     b.close()
 
 
+def test_clock_calls():
+    # teuk_get_clock / teuk_set_clock: step k's time is t0 + (k - step0) dt;
+    # set_time(t, s) is set_clock(t, s, s); a non-finite t0 is refused; the
+    # orbit table stays attached to the same steps across a clock change
+    import torch
+    from paper_0909_4039_amd import TeukError
+    from paper_0909_4039_amd.solver import suggest_dt
+    dt = suggest_dt(NR, NTH, RMIN, RMAX, A, M, MM, S, 1000)
+    a = make(dt)
+    a.set_source(9.0, 1.0)
+    a.set_state(*inputs.random_state(NR, NTH, 33))
+    assert a.get_clock() == (0.0, 0, 0)
+    a.step(3)
+    assert a.get_clock() == (0.0, 0, 3) and a.get_time() == (3 * dt, 3)
+    a.set_clock(1.25, 10, 14)
+    assert a.get_clock() == (1.25, 10, 14)
+    assert a.get_time() == (1.25 + 4 * dt, 14)
+    a.step(2)
+    assert a.get_time() == (1.25 + 6 * dt, 16)
+    a.set_time(2.5, 7)
+    assert a.get_clock() == (2.5, 7, 7) and a.get_time() == (2.5, 7)
+    with pytest.raises(TeukError) as e:
+        a.set_clock(float("nan"), 0, 0)
+    assert e.value.code == -1
+    assert a.get_clock() == (2.5, 7, 7)
+    # the orbit table: 4 steps' entries from the current step; moving the
+    # current step by set_clock moves the table's first step with it
+    a.set_trajectory(inputs.inspiral_trajectory(9.0, A, M, 0.05, dt, 4))
+    a.set_clock(0.0, 0, 100)
+    a.step(4)
+    with pytest.raises(TeukError):
+        a.step(1)                        # past the table
+    torch.cuda.synchronize()
+    a.check_finite()
+    a.close()
+
+
 def test_autotune_cache_reuses_a_choice(tmp_path):
     import torch
     from paper_0909_4039_amd import tune_cache
