@@ -67,7 +67,7 @@ def measured_traffic(prec, rows, order):
 # Two-step tilings (theta rows per wave, launch form: 0 one wavefront per
 # tile in chunk-major block order, 1 the same in group-major order, 2 a
 # pair) that --tiling-sweep times, and whose HBM counters the traffic record
-# holds: the autotuner's usual choices on 32768 x 1024.
+# holds: the autotuner's usual choices on 32768 x 1024 and their neighbours.
 SWEEP_TILINGS = {64: [(64, 0), (80, 0), (96, 0), (112, 0), (128, 0), (192, 0), (256, 0), (64, 1), (80, 1), (96, 1),
                       (112, 1), (128, 1), (192, 1), (64, 2), (96, 2)],
                  32: [(48, 0), (64, 0), (80, 0), (96, 0), (112, 0), (128, 0), (192, 0), (48, 1), (64, 1), (80, 1),

@@ -777,21 +777,34 @@ static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* 
     const int nth = (int)c->geo.nth;
     const int keep_rows = c->rows, keep_kb = c->kblock, keep_order = c->order;
     const bool keep_default = c->rows_default;
-    double best = 0.0;
-    int best_rows = keep_rows, best_kb = keep_kb, best_order = 0;
     // launch forms: one step per launch; two fused steps on one wavefront
-    // (order 0) or on a pair of wavefronts (order 2)
-    static const int kForms[][2] = {{1, 0}, {2, 0}, {2, 2}};
+    // (block order 0 chunk-major, 1 group-major) or on a pair of wavefronts
+    // (order 2).  Every candidate is timed twice, the second pass in the
+    // reverse order, and keeps its faster trial, so that neither a drift
+    // over the trials nor one slow trial decides (see the reverse sweep's
+    // tuner below).
+    static const int kForms[][2] = {{1, 0}, {2, 0}, {2, 1}, {2, 2}};
+    struct Cand {
+        int rows, kb, order;
+        double sec;
+    };
+    std::vector<Cand> cand;
     for (const auto& form : kForms) {
-        const int kb = form[0];
         int prev = 0;
         for (int r : kRows) {
             const int rows = std::min(r, nth);
             if (rows == prev) continue;   // candidates clipped to n_theta repeat
             prev = rows;
-            c->rows = rows;
-            c->kblock = kb;
-            c->order = form[1];
+            cand.push_back({rows, form[0], form[1], 0.0});
+        }
+    }
+    const int nc = (int)cand.size();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < nc; ++j) {
+            Cand& x = cand[pass == 0 ? j : nc - 1 - j];
+            c->rows = x.rows;
+            c->kblock = x.kb;
+            c->order = x.order;
             double sec = 0.0;
             int rc = (c->prec != TEUK_FP32) ? time_trial<double>(c, launches_per_trial, &sec)
                                      : time_trial<float>(c, launches_per_trial, &sec);
@@ -802,12 +815,17 @@ static int teuk_autotune_impl(teuk_ctx* c, int32_t launches_per_trial, int32_t* 
                 c->rows_default = keep_default;
                 return rc;
             }
-            if (best == 0.0 || sec < best) {
-                best = sec;
-                best_rows = rows;
-                best_kb = kb;
-                best_order = form[1];
-            }
+            if (pass == 0 || sec < x.sec) x.sec = sec;
+        }
+    }
+    double best = 0.0;
+    int best_rows = keep_rows, best_kb = keep_kb, best_order = 0;
+    for (const Cand& x : cand) {
+        if (best == 0.0 || x.sec < best) {
+            best = x.sec;
+            best_rows = x.rows;
+            best_kb = x.kb;
+            best_order = x.order;
         }
     }
     c->rows = best_rows;
