@@ -286,12 +286,14 @@ int teuk_param_gradient(teuk_ctx* ctx, int32_t param, double h, double rstar_obs
 
 /* Autotuner (synchronous): times launches_per_trial launches (after one
  * warm-up launch) of every candidate tile shape -- theta rows per wavefront
- * in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256} clipped to
- * n_theta, times three launch forms: 1 step per launch, 2 steps on one
- * wavefront, 2 steps on a pair of wavefronts (teuk_set_tiling orders 0 and
- * 2) -- with HIP events on the context's stream, keeps the fastest and
- * reports its rows and steps per launch in *rows_out and *kb_out (either may
- * be NULL; teuk_get_tiling reports the order).  The results of teuk_step are
+ * in {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 80, 96, 112, 128, 192, 256}
+ * clipped to n_theta, times four launch forms: 1 step per launch, 2 steps
+ * on one wavefront in chunk-major or group-major block order, 2 steps on a
+ * pair of wavefronts (teuk_set_tiling orders 0, 1 and 2) -- with HIP events
+ * on the context's stream, twice (the second pass in the reverse order,
+ * each candidate keeping its faster trial), keeps the fastest and reports
+ * its rows and steps per launch in *rows_out and *kb_out (either may be
+ * NULL; teuk_get_tiling reports the order).  The results of teuk_step are
  * bitwise identical for every candidate, so tuning changes speed only.
  * Needs a bound state; the trial launches read the current pair and write
  * the other one, so the state, time and waveform are unchanged.  The
@@ -308,8 +310,9 @@ int teuk_autotune(teuk_ctx* ctx, int32_t launches_per_trial, int32_t* rows_out, 
 int teuk_set_adjoint_tiling(teuk_ctx* ctx, int32_t rows_per_wave, int32_t steps_per_launch);
 int teuk_get_adjoint_tiling(teuk_ctx* ctx, int32_t* rows_per_wave, int32_t* steps_per_launch);
 
-/* Autotuner of the reverse sweep (FP64, synchronous): as teuk_autotune over
- * the same candidate rows times 1 or 2 reverse steps per launch, timing
+/* Autotuner of the reverse sweep (FP64, synchronous): as teuk_autotune
+ * (two passes) over its candidate rows but 80 and 112, times 1 or 2
+ * reverse steps per launch, timing
  * reverse-step launches that read the bound state's current pair as the
  * adjoint and write the other pair, so the state, time and waveform are
  * unchanged.  Allocates and frees a small device buffer for the trials'
